@@ -1,0 +1,38 @@
+"""Plain FP64 CPU oracle for two-stage Householder orthogonalization.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and its
+Python binding) may import, call or link anything here.  The only permitted
+users are ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py``.
+
+The oracle is written from He & Shao, "On Two-Stage Householder
+Orthogonalization" (arXiv 2602.14449).  Every function cites the passage it
+follows (section, equation, algorithm or table).  All arithmetic is IEEE
+double (real float64 or complex128), the precision the paper's experiments
+use (start of §6).  Library primitives (matrix products, triangular solves,
+LAPACK QR for very tall inputs, eigenvalues for 2-norms) are used as single
+steps; nothing is blocked, fused or reordered beyond what the paper states.
+
+Modules
+  householder  column Householder QR (the intra-block QR of line 6 of
+               Algorithm 1 and the QR of the top block for the second choice
+               of P), with the nonnegative-diagonal phase convention
+  two_stage    Algorithm 1 with the second choice of P (§3.1, §3.2)
+  baselines    Householder QR of [V, A] (start of §3) and the BCGS framework
+               with reorthogonalization patterns (eq. (1), Table 1)
+  metrics      loss of orthogonality and residual as printed in Tables 1-4
+  adjoint      reverse-mode gradient of the map Algorithm 1 computes, plus a
+               central finite-difference checker (the paper is silent on
+               gradients; see the module header)
+
+Parity status: every function here is pinned by ``tests/test_oracle_*.py``;
+the reduced-precision panel variants of the GPU library have no oracle of
+their own ("parity unpinned": their loss is reported against this FP64
+oracle).
+"""
+
+from .householder import householder_qr, qr_pos, phase_normalize  # noqa: F401
+from .two_stage import two_stage, two_stage_intermediates  # noqa: F401
+from .baselines import hhqr_full, bcgs  # noqa: F401
+from .metrics import (  # noqa: F401
+    orth_loss, orth_parts, rel_residual, gram_chunked, spectral_norm_tall)
