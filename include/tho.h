@@ -1,0 +1,113 @@
+/*
+ * tho.h -- C ABI of the two-stage Householder orthogonalization library
+ * (libtho.so), hand-written HIP kernels for AMD gfx950 (MI355X).
+ *
+ * Problem (He & Shao, "On Two-Stage Householder Orthogonalization", §1):
+ * given V (n x k0) with orthonormal columns and A (n x k), k0 + k << n, find
+ * Q (n x k) with orthonormal columns, Q orthogonal to V, and R (k x k upper
+ * triangular), S (k0 x k) such that
+ *        [V, A] = [V, Q] [[I, S], [0, R]]          (eq. (4))
+ * and [V, Q]^* [V, Q] = I.
+ *
+ * Conventions shared by every entry point
+ *   - All matrices are DEVICE pointers, row-major with unit column stride and
+ *     row stride ld (in elements), ld >= number of columns.  Element type is
+ *     IEEE double (THO_F64) or interleaved (re, im) double pairs (THO_C128,
+ *     the layout of std::complex<double> / torch.complex128).
+ *   - The caller owns every buffer.  Inputs (V, A, ...) are read-only.
+ *     Outputs (Q, R, S, ...) are fully overwritten; the strictly lower part
+ *     of R is written as zero.  Outputs must not alias inputs or each other.
+ *   - diag(R) is real and nonnegative and Q is scaled consistently (the
+ *     phase convention used throughout; the paper uses QR variants with a
+ *     nonnegative R diagonal for P, §3.2 and §6).
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *     the default stream).  Calls return after enqueueing; they never
+ *     synchronize the device and never allocate device memory (the
+ *     workspace is caller-provided).  Calls with distinct workspaces may run
+ *     concurrently.
+ *   - Return value: 0 on success; -i when argument i (1-based) is invalid
+ *     (LAPACK style: sizes, ld too small, NULL pointer, bad alignment);
+ *     THO_E_WORKSPACE when ws_bytes is too small; THO_E_HIP when a HIP call
+ *     failed (see tho_last_error()); THO_E_UNSUPPORTED for a valid but
+ *     unimplemented combination.  Numerical conditions (non-finite input)
+ *     are not errors of the call; they propagate as NaN like LAPACK.
+ */
+#ifndef THO_H
+#define THO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { THO_F64 = 0, THO_C128 = 1 } tho_dtype_t;
+
+/* Choice of the unitary P of line 1 of Algorithm 1 (§3.2).  Only the second
+ * choice (QR of the top block, P = -Q1, T = I + R1^*) is implemented; it is
+ * the one the paper recommends (§6.2, §7). */
+typedef enum { THO_P_QR = 0 } tho_pchoice_t;
+
+/* Arithmetic of the four n x k0 x k panel products of Algorithm 1 (V^*A,
+ * the update A + V Z, V^*Q_ and Q_ + V N).  Reflector generation, norms and
+ * the T factors always stay FP64.  THO_PANEL_F32X2 splits each FP64 operand
+ * into an FP32 hi + lo pair (three FP32 MFMA products, FP32 accumulation
+ * inside each MFMA block, FP64 across blocks); THO_PANEL_BF16 rounds the
+ * operands to BF16 (FP32 accumulation).  Reduced-precision panels trade the
+ * orthogonality of Q (about 1e-7 and 1e-3 respectively) for speed. */
+typedef enum { THO_PANEL_F64 = 0, THO_PANEL_F32X2 = 1, THO_PANEL_BF16 = 2 } tho_panel_t;
+
+typedef struct {
+    int32_t p_choice;   /* tho_pchoice_t */
+    int32_t panel;      /* tho_panel_t   */
+    int32_t flags;      /* reserved, must be 0 */
+    int32_t reserved;
+} tho_opts_t;
+
+#define THO_E_WORKSPACE   (-100)
+#define THO_E_HIP         (-101)
+#define THO_E_UNSUPPORTED (-102)
+
+/* Largest supported k0 and k (the k0 x k0 and k x k factorizations run
+ * inside one workgroup; see the design notes). */
+#define THO_MAX_K0 128
+#define THO_MAX_K  64
+
+/* Bytes of device workspace tho_two_stage needs for these sizes (opts may be
+ * NULL for defaults).  Returns 0 or -i like the other calls. */
+int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+                            const tho_opts_t* opts, size_t* bytes);
+
+/* Algorithm 1 of the paper (§3.1) with the second choice of P (§3.2):
+ *   P = -Q1 where V_top = Q1 R1 (diag R1 >= 0), W = [P; 0] - V, T = I + R1^*,
+ *   A <- (I - W T^{-*} W^*) A,  S = P^* A_top,  A_low = Q_ R (Householder),
+ *   Q = (I - W T^{-1} W^*) [0; Q_].
+ * Arguments: 1 dtype, 2 n, 3 k0, 4 k, 5 V (n x k0), 6 ldv, 7 A (n x k),
+ * 8 lda, 9 Q (n x k, out), 10 ldq, 11 R (k x k, out), 12 ldr, 13 S (k0 x k,
+ * out), 14 lds, 15 opts (NULL = defaults), 16 ws, 17 ws_bytes, 18 stream.
+ * Requires n >= k0 + k, 0 <= k0 <= THO_MAX_K0, 0 <= k <= THO_MAX_K.
+ * k0 == 0 computes a plain Householder QR of A; k == 0 is a no-op.  V is
+ * assumed orthonormal; if it is not, Q loses orthogonality in proportion to
+ * ||V^*V - I|| (Theorem 1 and the remark after it) -- not an error.
+ * A rank-deficient A is not an error: Q is still orthonormal and orthogonal
+ * to V (§1, the reason for Householder-QR as the intra-block step). */
+int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+                  const void* V, int64_t ldv, const void* A, int64_t lda,
+                  void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
+                  const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last THO_E_HIP / argument error on this thread. */
+const char* tho_last_error(void);
+
+/* Static description of an error code. */
+const char* tho_strerror(int code);
+
+/* Library version string. */
+const char* tho_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THO_H */

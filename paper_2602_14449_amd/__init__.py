@@ -1,0 +1,13 @@
+"""Two-stage Householder orthogonalization on AMD MI355X (gfx950).
+
+Python binding of libtho (hand-written HIP kernels behind a C ABI, declared
+in include/tho.h).  This layer only marshals arguments: it allocates outputs
+and workspace with PyTorch on the tensors' device and calls the C entry
+points on the current HIP stream.  Importing the package fails if libtho.so
+has not been built.
+"""
+
+from . import _lib  # noqa: F401  (raises ImportError when libtho.so is absent)
+from .api import two_stage, workspace_bytes  # noqa: F401
+
+__all__ = ["two_stage", "workspace_bytes"]

@@ -1,0 +1,62 @@
+"""ctypes loader for libtho.so (the HIP library).  No fallback: if the shared
+library is missing or fails to load, importing the package raises."""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtho.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libtho.so not found at %s; build it first with "
+        "`python -m paper_2602_14449_amd.build`" % LIB_PATH)
+
+lib = ctypes.CDLL(LIB_PATH)
+
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_vp = ctypes.c_void_p
+c_sz = ctypes.c_size_t
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("p_choice", c_i32), ("panel", c_i32), ("flags", c_i32),
+                ("reserved", c_i32)]
+
+
+def _proto(name, restype, argtypes):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+tho_version = _proto("tho_version", ctypes.c_char_p, [])
+tho_last_error = _proto("tho_last_error", ctypes.c_char_p, [])
+tho_strerror = _proto("tho_strerror", ctypes.c_char_p, [ctypes.c_int])
+tho_two_stage_workspace = _proto(
+    "tho_two_stage_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_two_stage = _proto(
+    "tho_two_stage", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+     c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+
+EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
+            "tho_two_stage_workspace", "tho_two_stage"]
+
+THO_F64 = 0
+THO_C128 = 1
+PANELS = {"fp64": 0, "f32x2": 1, "bf16": 2}
+
+
+class ThoError(RuntimeError):
+    pass
+
+
+def check(rc, what):
+    if rc != 0:
+        msg = tho_last_error().decode(errors="replace")
+        raise ThoError("%s failed (%d: %s): %s" % (
+            what, rc, tho_strerror(rc).decode(), msg))

@@ -1,0 +1,404 @@
+// Small dense kernels: split-n reductions of X^T Y (the V^*A products of
+// Algorithm 1), their fixed-order finish, and the k0 x k0 / k0 x k work
+// done by one workgroup (QR of the top block for the second choice of P,
+// triangular solves with T, small products).
+#include "tho_device.h"
+#include "tho_internal.h"
+
+namespace tho {
+
+// --------------------------------------------------------------------------
+// part[blk] = X[r0:r1]^T Y[r0:r1] for the row range of block blk.
+// X: nrows x p (ld ldx), Y: nrows x q (ld ldy), p <= 16*MT, q <= 16*NT.
+// Four waves: WM wave groups split the MT row-tiles of the output, the
+// remaining 4/WM groups split the rows and are summed through LDS.
+// Every K-step consumes 4 rows; operands are read straight from HBM in the
+// MFMA operand layouts (16 consecutive doubles of one row per lane group).
+// Output: part[blk][16*MT][16*NT], row-major.
+// --------------------------------------------------------------------------
+template <int MT, int NT, int WM>
+__global__ __launch_bounds__(256) void k_xty_partial(
+    int64_t nrows, const double* __restrict__ X, int64_t ldx, int p,
+    const double* __restrict__ Y, int64_t ldy, int q, int64_t rows_per_blk,
+    double* __restrict__ part) {
+    constexpr int MTW = MT / WM;
+    constexpr int WR = 4 / WM;
+    constexpr int RED = (WR > 1) ? (WR - 1) * WM * MTW * NT * 64 : 1;
+    __shared__ d4 red[RED];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w % WM, wr = w / WM;
+    const int g = l >> 4, cl = l & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = (r0 + rows_per_blk < nrows) ? r0 + rows_per_blk : nrows;
+
+    d4 acc[MTW][NT];
+#pragma unroll
+    for (int i = 0; i < MTW; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = d4zero();
+
+    int colx[MTW];
+    bool okx[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; i++) {
+        colx[i] = 16 * (wm * MTW + i) + cl;
+        okx[i] = colx[i] < p;
+    }
+    int coly[NT];
+    bool oky[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) {
+        coly[j] = 16 * j + cl;
+        oky[j] = coly[j] < q;
+    }
+    // 16 rows (4 K-steps) per iteration of this wave; wave groups interleave
+    constexpr int U = 4;
+    for (int64_t rb = r0 + (int64_t)wr * 4 * U; rb < r1; rb += (int64_t)WR * 4 * U) {
+        double xa[U][MTW], yb[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t row = rb + 4 * u + g;
+            const bool rv = row < r1;
+#pragma unroll
+            for (int i = 0; i < MTW; i++)
+                xa[u][i] = (rv && okx[i]) ? X[row * ldx + colx[i]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NT; j++)
+                yb[u][j] = (rv && oky[j]) ? Y[row * ldy + coly[j]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int i = 0; i < MTW; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++) acc[i][j] = mfma(xa[u][i], yb[u][j], acc[i][j]);
+    }
+    if (WR > 1) {
+        if (wr > 0) {
+#pragma unroll
+            for (int i = 0; i < MTW; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    red[(((wr - 1) * WM + wm) * MTW * NT + i * NT + j) * 64 + l] = acc[i][j];
+        }
+        __syncthreads();
+        if (wr == 0) {
+            for (int r = 1; r < WR; r++)
+#pragma unroll
+                for (int i = 0; i < MTW; i++)
+#pragma unroll
+                    for (int j = 0; j < NT; j++)
+                        acc[i][j] += red[(((r - 1) * WM + wm) * MTW * NT + i * NT + j) * 64 + l];
+        }
+    }
+    if (wr == 0) {
+        double* out = part + (int64_t)blockIdx.x * (16 * MT) * (16 * NT);
+#pragma unroll
+        for (int i = 0; i < MTW; i++)
+#pragma unroll
+            for (int j = 0; j < NT; j++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int row = 16 * (wm * MTW + i) + drow(l, v);
+                    out[row * (16 * NT) + 16 * j + cl] = acc[i][j][v];
+                }
+    }
+}
+
+// out[i] = sum over parts of part[p][i], in part order (deterministic).
+__global__ void k_reduce_parts(int nparts, int64_t elems, const double* __restrict__ part,
+                               double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= elems) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; p++) s += part[(int64_t)p * elems + i];
+    out[i] = s;
+}
+
+// D = alpha op(A) op(B) + beta C for small matrices, one thread per output.
+// op(A) is M x K: A[i*lda + p] (or A[p*lda + i] if ta); op(B) is K x N.
+// C may alias D (elementwise read-then-write by the same thread).
+__global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __restrict__ A,
+                             int64_t lda, int ta, const double* __restrict__ B, int64_t ldb,
+                             int tb, double beta, const double* C, int64_t ldc, double* D,
+                             int64_t ldd) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * N) return;
+    const int i = (int)(t / N), j = (int)(t % N);
+    double s = 0.0;
+    for (int p = 0; p < K; p++) {
+        const double a = ta ? A[(int64_t)p * lda + i] : A[(int64_t)i * lda + p];
+        const double b = tb ? B[(int64_t)j * ldb + p] : B[(int64_t)p * ldb + j];
+        s = fma(a, b, s);
+    }
+    double r = alpha * s;
+    if (beta != 0.0) r = fma(beta, C[(int64_t)i * ldc + j], r);
+    D[(int64_t)i * ldd + j] = r;
+}
+
+// In-place solve with a lower-triangular L (n x n, ld ldl) on B (n x m):
+//   trans == 0:  L X = B   (forward substitution)
+//   trans == 1:  L^T X = B (backward substitution; L^T is upper)
+// One workgroup; B staged in LDS (n*m doubles, dynamic).
+__global__ __launch_bounds__(1024) void k_trsm_lower(int n, int m, const double* __restrict__ L,
+                                                     int64_t ldl, int trans, double* B,
+                                                     int64_t ldb) {
+    extern __shared__ double sm[];
+    double* Bs = sm;  // n x m
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < n * m; e += nt) Bs[e] = B[(int64_t)(e / m) * ldb + (e % m)];
+    __syncthreads();
+    for (int it = 0; it < n; it++) {
+        const int i = trans ? (n - 1 - it) : it;
+        if (tid < m) Bs[i * m + tid] /= L[(int64_t)i * ldl + i];
+        __syncthreads();
+        const int cnt = trans ? i : (n - 1 - i);
+        for (int e = tid; e < cnt * m; e += nt) {
+            const int r = e / m, c = e % m;
+            const int pr = trans ? r : (i + 1 + r);
+            const double lv = trans ? L[(int64_t)i * ldl + pr] : L[(int64_t)pr * ldl + i];
+            Bs[pr * m + c] -= lv * Bs[i * m + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * m; e += nt) B[(int64_t)(e / m) * ldb + (e % m)] = Bs[e];
+}
+
+// Householder QR of the square top block V_top (n x n, n <= 128) with
+// nonnegative diag(R) (the second choice of P, §3.2), entirely in LDS, then
+//   P = -Q1  and  T = I + R1^T  (lower triangular; the form of Appendix B.2)
+// written to P (ld n) and T (ld n).  Reflectors use the same convention as
+// the rest of the library (beta = -sign(alpha) * norm, tau = 0 for a zero
+// subcolumn); Q is formed in place from the reflectors (backward
+// accumulation), then columns of Q / rows of R are scaled by sign(R_jj).
+__global__ __launch_bounds__(1024) void k_qr_top(int n, const double* __restrict__ Vt, int64_t ldv,
+                                                 double* __restrict__ P, double* __restrict__ T) {
+    extern __shared__ double sm[];
+    const int ld = n + 1;
+    double* M = sm;                 // n x ld
+    double* part = M + n * ld;      // 8 x n partial dots
+    double* wv = part + 8 * n;      // n: w_c of the current reflector
+    double* taus = wv + n;          // n
+    double* sgn = taus + n;         // n: sign of R_jj
+    double* red = sgn + n;          // 16 scalars
+    const int tid = threadIdx.x;
+    const int c = tid % 128, rg = tid / 128;  // column, row group (8 groups)
+    for (int e = tid; e < n * n; e += blockDim.x) M[(e / n) * ld + (e % n)] = Vt[(int64_t)(e / n) * ldv + (e % n)];
+    __syncthreads();
+    for (int j = 0; j < n; j++) {
+        // sum of squares of the subcolumn below the pivot
+        double ss = 0.0;
+        if (tid < 64) {
+            for (int i = j + 1 + tid; i < n; i += 64) ss += M[i * ld + j] * M[i * ld + j];
+            ss = sum_wave(ss);
+            if (tid == 0) red[0] = ss;
+        }
+        __syncthreads();
+        const double sig2 = red[0];
+        const double alpha = M[j * ld + j];
+        double beta = alpha, tau = 0.0, scale = 0.0;
+        if (sig2 != 0.0) {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = (alpha < 0.0) ? nrm : -nrm;
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        __syncthreads();  // everyone has read M[j][j] and red
+        if (tid > j && tid < n) M[tid * ld + j] *= scale;
+        if (tid == 0) { taus[j] = tau; M[j * ld + j] = beta; }
+        __syncthreads();
+        // w_c = M[j][c] + sum_{i>j} v_i M[i][c] for c > j
+        if (c < n && c > j) {
+            double s = 0.0;
+            for (int i = j + 1 + rg; i < n; i += 8) s += M[i * ld + j] * M[i * ld + c];
+            part[rg * n + c] = s;
+        }
+        __syncthreads();
+        if (tid < n && tid > j) {
+            double s = M[j * ld + tid];
+            for (int r = 0; r < 8; r++) s += part[r * n + tid];
+            wv[tid] = s;
+        }
+        __syncthreads();
+        if (c < n && c > j) {
+            const double tw = tau * wv[c];
+            if (rg == 0) M[j * ld + c] -= tw;
+            for (int i = j + 1 + rg; i < n; i += 8) M[i * ld + c] -= tw * M[i * ld + j];
+        }
+        __syncthreads();
+    }
+    // R1 diagonal signs and T = I + D R1^T (rows of R scaled by d)
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, jj = e % n;  // T[i][jj] = delta + d_jj R[jj][i] for jj <= i
+        double v = (i == jj) ? 1.0 : 0.0;
+        if (jj <= i) {
+            const double d = (M[jj * ld + jj] < 0.0) ? -1.0 : 1.0;
+            v += d * M[jj * ld + i];
+        }
+        T[(int64_t)i * n + jj] = v;
+    }
+    // keep the diagonal signs before Q overwrites M
+    if (tid < n) sgn[tid] = (M[tid * ld + tid] < 0.0) ? -1.0 : 1.0;
+    __syncthreads();
+    // form Q in place (backward accumulation of the reflectors)
+    for (int j = n - 1; j >= 0; j--) {
+        const double tau = taus[j];
+        if (j < n - 1) {
+            if (c < n && c > j) {
+                double s = 0.0;
+                for (int i = j + 1 + rg; i < n; i += 8) s += M[i * ld + j] * M[i * ld + c];
+                part[rg * n + c] = s;
+            }
+            __syncthreads();
+            if (tid < n && tid > j) {
+                // row j of an already formed column c > j is zero
+                double s = M[j * ld + tid];
+                for (int r = 0; r < 8; r++) s += part[r * n + tid];
+                wv[tid] = s;
+            }
+            __syncthreads();
+            if (c < n && c > j) {
+                const double tw = tau * wv[c];
+                if (rg == 0) M[j * ld + c] -= tw;
+                for (int i = j + 1 + rg; i < n; i += 8) M[i * ld + c] -= tw * M[i * ld + j];
+            }
+            __syncthreads();
+        }
+        if (tid < n) {
+            if (tid > j) M[tid * ld + j] = -tau * M[tid * ld + j];
+            else if (tid == j) M[j * ld + j] = 1.0 - tau;
+            else M[tid * ld + j] = 0.0;
+        }
+        __syncthreads();
+    }
+    // P = -Q D
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, jj = e % n;
+        P[(int64_t)i * n + jj] = -M[i * ld + jj] * sgn[jj];
+    }
+}
+
+// Phase-normalize the top-level R (k x k, rows of ld KP in Rin) and write
+//   Rout = D Rin (upper part, zero below), G0 = D (KP x KP, zero padded),
+// where D = diag(sign(R_jj)) with sign(0) = +1.
+__global__ void k_finish_r(int k, int KP, const double* __restrict__ Rin, int64_t ldri,
+                           double* __restrict__ Rout, int64_t ldr, double* __restrict__ G0) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        const double d = (Rin[(int64_t)i * ldri + i] < 0.0) ? -1.0 : 1.0;
+        Rout[(int64_t)i * ldr + j] = (j >= i) ? d * Rin[(int64_t)i * ldri + j] : 0.0;
+    }
+    for (int e = tid; e < KP * KP; e += blockDim.x) {
+        const int i = e / KP, j = e % KP;
+        double v = 0.0;
+        if (i == j && i < k) v = (Rin[(int64_t)i * ldri + i] < 0.0) ? -1.0 : 1.0;
+        G0[e] = v;
+    }
+}
+
+// prod[c] = Nc[c] (K0P x KP) * G_c (KP x KP, rows of ld ldg starting at row
+// c*k of Gbase; only the first k rows/cols are meaningful), one block per chunk.
+__global__ void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ Nc,
+                             const double* __restrict__ Gbase, int64_t ldg, int64_t grow_stride,
+                             double* __restrict__ prod) {
+    const int c = blockIdx.x;
+    const double* N = Nc + (int64_t)c * K0P * KP;
+    const double* G = Gbase + (int64_t)c * grow_stride * ldg;
+    double* out = prod + (int64_t)c * K0P * KP;
+    for (int e = threadIdx.x; e < K0P * KP; e += blockDim.x) {
+        const int i = e / KP, j = e % KP;
+        double s = 0.0;
+        if (j < k)
+            for (int p = 0; p < k; p++) s = fma(N[i * KP + p], G[(int64_t)p * ldg + j], s);
+        out[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define XTY_CASE(MT, NT, WM)                                                               \
+    if (mt == MT && nt == NT) {                                                             \
+        hipLaunchKernelGGL((k_xty_partial<MT, NT, WM>), dim3(nblk), dim3(256), 0, st, nrows, X, \
+                           ldx, p, Y, ldy, q, rows_per_blk, part);                          \
+        return hipGetLastError();                                                           \
+    }
+
+hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
+                              const double* Y, int64_t ldy, int q, int nblk, int64_t rows_per_blk,
+                              double* part, hipStream_t st) {
+    XTY_CASE(1, 1, 1)
+    XTY_CASE(1, 2, 1)
+    XTY_CASE(1, 4, 1)
+    XTY_CASE(2, 1, 2)
+    XTY_CASE(2, 2, 2)
+    XTY_CASE(2, 4, 2)
+    XTY_CASE(4, 1, 4)
+    XTY_CASE(4, 2, 4)
+    XTY_CASE(4, 4, 4)
+    XTY_CASE(8, 1, 4)
+    XTY_CASE(8, 2, 4)
+    XTY_CASE(8, 4, 4)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_parts(int nparts, int64_t elems, const double* part, double* out,
+                               hipStream_t st) {
+    const int bs = 256;
+    const int64_t nb = (elems + bs - 1) / bs;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)nb), dim3(bs), 0, st, nparts, elems, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, int ta,
+                             const double* B, int64_t ldb, int tb, double beta, const double* C,
+                             int64_t ldc, double* D, int64_t ldd, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int bs = 256;
+    const int64_t nb = ((int64_t)M * N + bs - 1) / bs;
+    hipLaunchKernelGGL(k_small_gemm, dim3((unsigned)nb), dim3(bs), 0, st, M, N, K, alpha, A, lda, ta,
+                       B, ldb, tb, beta, C, ldc, D, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int trans, double* B,
+                             int64_t ldb, hipStream_t st) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    const size_t shm = (size_t)n * m * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_trsm_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_trsm_lower, dim3(1), dim3(1024), shm, st, n, m, L, ldl, trans, B, ldb);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double* T, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const size_t shm = ((size_t)n * (n + 1) + 8 * n + 3 * n + 16) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_qr_top, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_qr_top, dim3(1), dim3(1024), shm, st, n, Vt, ldv, P, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
+                           double* G0, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish_r, dim3(1), dim3(256), 0, st, k, KP, Rin, ldri, Rout, ldr, G0);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
+                             int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_prod, dim3(nchunk), dim3(256), 0, st, K0P, KP, k, Nc, Gbase, ldg,
+                       grow_stride, prod);
+    return hipGetLastError();
+}
+
+}  // namespace tho

@@ -1,0 +1,69 @@
+// Host-side declarations of the kernel launchers inside libtho (not part of
+// the public C ABI; see include/tho.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tho {
+
+// Tile geometry of the tall-skinny Householder kernels: a workgroup of
+// LEAF_WAVES wavefronts owns a tile of LEAF_ROWS rows; each wavefront holds
+// 32 rows (two 16-row MFMA blocks) of the tile in registers.
+constexpr int LEAF_WAVES = 8;
+constexpr int LEAF_ROWS = 256;
+
+// Arguments of one level of the chunked tall-skinny QR (leaf) and of the
+// matching Q formation (form).  Level 0 works on the bottom n - k0 rows of A
+// (forming A + V Z on the fly) and stores Householder vectors into the Q
+// output; levels >= 1 work in place on the stacked R factors of the level
+// below.
+struct TsqrLevel {
+    int64_t m;        // rows of this level's matrix
+    int k;            // columns (<= KP)
+    int nchunk;       // chunks (one workgroup each)
+    int maxtiles;     // tile slots reserved per chunk
+    const double* X;  // input rows (leaf); ld ldx
+    int64_t ldx;
+    double* Y;        // Householder vectors out (leaf) / Q rows out (form); ld ldy
+    int64_t ldy;
+    // level 0 with k0 > 0 only
+    const double* V;  // bottom rows of V; ld ldv
+    int64_t ldv;
+    int k0;
+    const double* Z;  // K0P x KP: the k0 x k solve result of line 4
+    double* Nc;       // per chunk K0P x KP: V_chunk^T Q_chunk (leaf output)
+    const double* Nglob;  // K0P x KP: T^{-1} G (form input)
+    // per-tile storage
+    double* tau;      // [nchunk * maxtiles][KP]
+    double* Tt;       // [nchunk * maxtiles][KP * KP]
+    // leaf: R factor of chunk c goes to rows c*k .. c*k+k-1 of Rnext (ld ldrn)
+    double* Rnext;
+    int64_t ldrn;
+    // form: G_c of chunk c is rows c*gstride .. of Gin (ld ldg)
+    const double* Gin;
+    int64_t ldg;
+    int64_t gstride;
+};
+
+hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
+                              const double* Y, int64_t ldy, int q, int nblk, int64_t rows_per_blk,
+                              double* part, hipStream_t st);
+hipError_t launch_reduce_parts(int nparts, int64_t elems, const double* part, double* out,
+                               hipStream_t st);
+hipError_t launch_small_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, int ta,
+                             const double* B, int64_t ldb, int tb, double beta, const double* C,
+                             int64_t ldc, double* D, int64_t ldd, hipStream_t st);
+hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int trans, double* B,
+                             int64_t ldb, hipStream_t st);
+hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double* T, hipStream_t st);
+hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
+                           double* G0, hipStream_t st);
+hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
+                             int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st);
+
+// kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term)
+hipError_t launch_tsqr_leaf(int kp, int k0p, const TsqrLevel& L, hipStream_t st);
+hipError_t launch_tsqr_form(int kp, int k0p, const TsqrLevel& L, hipStream_t st);
+
+}  // namespace tho
