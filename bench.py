@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-stage Householder orthogonalization on one MI355X.
+
+One step = one call of tho_two_stage (Algorithm 1 with the second choice of
+P, every row-streaming step in libtho's HIP kernels) on the graded workload:
+real FP64, n = 2^22, k0 = 128, k = 64, V the Q factor of a Gaussian matrix,
+A = X diag(s) Y^T with s log-spaced from 1 to 1e-8 (cond(A) = 1e8).  Inputs
+are generated on the GPU from a fixed seed and are resident in HBM before
+the timed region.
+
+value  = algorithmic bytes / time, B_alg = 8 n (3 k0 + 4 k): V and A streamed
+         once in each of the three phases their dependences force and Q
+         written once.
+roofline: the dominant kernel (largest share of the timed region, from HIP
+         events the library records around each of its launches on the
+         call's stream), its algorithmic flops per launch over its average
+         duration, against the FP64 peak (the path is above the FP64 ridge).
+cpu_baseline: the CPU oracle (NumPy FP64, test infrastructure) timed on this
+         host on a 2^20-row sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=1 << 22)
+    p.add_argument("--k0", type=int, default=128)
+    p.add_argument("--k", type=int, default=64)
+    p.add_argument("--cpu-rows", type=int, default=1 << 20)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-check", action="store_true")
+    return p.parse_args()
+
+
+def make_inputs(n, k0, k, seed=3, device="cuda"):
+    """Graded workload on the GPU (input generation only)."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(260214449 + seed)
+    V, _ = torch.linalg.qr(torch.randn(n, k0, dtype=torch.float64, device=device, generator=g))
+    X, _ = torch.linalg.qr(torch.randn(n, k, dtype=torch.float64, device=device, generator=g))
+    Y, _ = torch.linalg.qr(torch.randn(k, k, dtype=torch.float64, device=device, generator=g))
+    s = 10.0 ** (-8.0 * torch.arange(k, dtype=torch.float64, device=device) / max(k - 1, 1))
+    A = (X * s[None, :]) @ Y.T.contiguous()
+    del X
+    return V.contiguous(), A.contiguous()
+
+
+def kernel_model(name, n, k0, k):
+    """Algorithmic (bytes, flops) per launch of the main kernels."""
+    m = n - k0
+    if name == "xty_partial":      # C = V^T A over all rows
+        return 8.0 * n * (k0 + k), 2.0 * n * k0 * k
+    if name == "leaf_l0":          # A + V Z, Householder QR, V^T Q chain
+        return 8.0 * m * (k0 + 2 * k), m * (4.0 * k0 * k + 2.0 * k * k)
+    if name == "form_l0":          # Q_ = Q_loc G, + V N
+        return 8.0 * m * (k0 + 2 * k), m * (2.0 * k0 * k + 2.0 * k * k)
+    return None
+
+
+def cpu_baseline(n_s, k0, k):
+    import numpy as np
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import two_stage as oracle_two_stage
+    V, A = make_inputs(n_s, k0, k, seed=33)
+    Vh, Ah = V.cpu().numpy(), A.cpu().numpy()
+    del V, A
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    oracle_two_stage(Vh, Ah)
+    t = time.perf_counter() - t0
+    gbs = 8.0 * n_s * (3 * k0 + 4 * k) / t / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "sample": "graded workload at n=%d (1/%d of the rows), k0=%d, k=%d; one oracle run, %.1f s"
+                      % (n_s, max(1, (1 << 22) // n_s), k0, k, t)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2602_14449_amd as tho
+    from paper_2602_14449_amd import _lib
+
+    n, k0, k = a.n, a.k0, a.k
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    V, A = make_inputs(n, k0, k)
+    Q = torch.empty(n, k, dtype=torch.float64, device=dev)
+    R = torch.empty(k, k, dtype=torch.float64, device=dev)
+    S = torch.empty(k0, k, dtype=torch.float64, device=dev)
+    ws = torch.empty(tho.workspace_bytes(n, k0, k), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(a.warmup):
+        tho.two_stage(V, A, out=(Q, R, S), workspace=ws)
+    torch.cuda.synchronize()
+
+    _lib.tho_profile_reset()
+    _lib.tho_profile_enable(1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(a.steps):
+        tho.two_stage(V, A, out=(Q, R, S), workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _lib.tho_profile_enable(0)
+    ms = e0.elapsed_time(e1) / a.steps
+    prof = _lib.profile_read()
+
+    B_alg = 8.0 * n * (3 * k0 + 4 * k)
+    F_alg = float(n) * (8 * k0 * k + 4 * k * k)
+    gbs = B_alg / (ms * 1e-3) / 1e9
+
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dcnt) = dom
+    davg = dms / max(dcnt, 1)
+    model = kernel_model(dname, n, k0, k)
+    roof = None
+    if model is not None:
+        bts, fl = model
+        ach = fl / (davg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4), "traffic": None,
+                "kernel": dname, "avg_ms": round(davg, 4),
+                "alg_bytes_per_launch": bts, "alg_flops_per_launch": fl}
+        tf = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+        if os.path.exists(tf):
+            try:
+                tj = json.load(open(tf))
+                ent = tj.get(dname)
+                if ent and ent.get("valid", False):
+                    roof["traffic"] = ent["bytes_per_launch"]
+            except Exception:
+                pass
+
+    check = {}
+    if not a.no_check:
+        from_q = torch.cat([V, Q], 1)
+        G = None
+        for i in range(0, n, 1 << 18):
+            blk = from_q[i:i + (1 << 18)]
+            gg = blk.T.contiguous() @ blk
+            G = gg if G is None else G + gg
+        Gm = G.cpu().numpy() - np.eye(k0 + k)
+        loss = float(np.max(np.abs(np.linalg.eigvalsh(0.5 * (Gm + Gm.T)))))
+        E = A - V @ S - Q @ R
+        ge = None
+        ga = None
+        for i in range(0, n, 1 << 18):
+            eb = E[i:i + (1 << 18)]
+            ab = A[i:i + (1 << 18)]
+            x = eb.T.contiguous() @ eb
+            y = ab.T.contiguous() @ ab
+            ge = x if ge is None else ge + x
+            ga = y if ga is None else ga + y
+        res = float(np.sqrt(np.max(np.linalg.eigvalsh(ge.cpu().numpy())) /
+                            np.max(np.linalg.eigvalsh(ga.cpu().numpy()))))
+        check = {"orth_loss": loss, "rel_residual": res}
+        del E, from_q
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        del Q
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(min(a.cpu_rows, n), k0, k)
+
+    out = {
+        "metric": "two-stage orth GB/s (% HBM peak) vs full HHQR of [V,A]; orth loss vs FP64",
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "graded: real FP64 two-stage, n=2^22, k0=128, k=64, "
+                               "cond(A)=1e8, FP64 panels" if (n, k0, k) == (1 << 22, 128, 64)
+                   else "graded: n=%d, k0=%d, k=%d" % (n, k0, k),
+                   "n": n, "k0": k0, "k": k, "panel": "fp64"},
+        "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+        "pct_fp64_peak": round(100.0 * F_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 2),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": check,
+        "kernels_ms_per_step": {kname: round(v[0] / a.steps, 4) for kname, v in
+                                sorted(prof.items(), key=lambda kv: -kv[1][0])},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

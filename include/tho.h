@@ -97,6 +97,19 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* Benchmark instrumentation (not needed for normal use).
+ * tho_profile_enable(1) makes every later call record a pair of hipEvents on
+ * its stream around each kernel it launches.  tho_profile_collect() waits
+ * for the recorded events, folds their elapsed times into per-kernel-name
+ * totals and returns the number of distinct names (or a negative error);
+ * tho_profile_get(i, ...) reads entry i (name into a caller buffer of
+ * name_len bytes, accumulated milliseconds, number of launches);
+ * tho_profile_reset() clears the totals.  Process-global, thread-safe. */
+int tho_profile_enable(int on);
+int tho_profile_collect(void);
+int tho_profile_reset(void);
+int tho_profile_get(int i, char* name, int name_len, double* total_ms, int64_t* launches);
+
 /* Message for the last THO_E_HIP / argument error on this thread. */
 const char* tho_last_error(void);
 

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libtho.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         "libtho.so not found at %s; build it first with "
-        "`python -m paper_2602_14449_amd.build`" % LIB_PATH)
+        "`python paper_2602_14449_amd/build.py`" % LIB_PATH)
 
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -60,3 +60,27 @@ def check(rc, what):
         msg = tho_last_error().decode(errors="replace")
         raise ThoError("%s failed (%d: %s): %s" % (
             what, rc, tho_strerror(rc).decode(), msg))
+
+tho_profile_enable = _proto("tho_profile_enable", ctypes.c_int, [ctypes.c_int])
+tho_profile_collect = _proto("tho_profile_collect", ctypes.c_int, [])
+tho_profile_reset = _proto("tho_profile_reset", ctypes.c_int, [])
+tho_profile_get = _proto("tho_profile_get", ctypes.c_int,
+                         [ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64)])
+EXPORTED += ["tho_profile_enable", "tho_profile_collect", "tho_profile_reset",
+             "tho_profile_get"]
+
+
+def profile_read():
+    """Collect recorded kernel timings: {name: (total_ms, launches)}."""
+    n = tho_profile_collect()
+    if n < 0:
+        check(n, "tho_profile_collect")
+    out = {}
+    buf = ctypes.create_string_buffer(64)
+    for i in range(n):
+        ms = ctypes.c_double(0)
+        cnt = c_i64(0)
+        check(tho_profile_get(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt)), "tho_profile_get")
+        out[buf.value.decode()] = (ms.value, cnt.value)
+    return out

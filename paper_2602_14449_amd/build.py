@@ -1,6 +1,7 @@
 """Build libtho.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2602_14449_amd.build  (or call build()).
+Usage: python paper_2602_14449_amd/build.py  (a plain script: it must not import
+the package, whose import loads the library being rebuilt).
 Every HIP translation unit is compiled with
   --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang -packed-fp32-ops
 (the last flag keeps the compiler from emitting packed FP32 instructions).

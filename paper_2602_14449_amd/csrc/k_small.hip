@@ -110,9 +110,13 @@ __global__ void k_reduce_parts(int nparts, int64_t elems, const double* __restri
                                double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= elems) return;
-    double s = 0.0;
-    for (int p = 0; p < nparts; p++) s += part[(int64_t)p * elems + i];
-    out[i] = s;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int p = 0;
+    for (; p + 8 <= nparts; p += 8)
+#pragma unroll
+        for (int u = 0; u < 8; u++) s[u] += part[(int64_t)(p + u) * elems + i];
+    for (; p < nparts; p++) s[0] += part[(int64_t)p * elems + i];
+    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // D = alpha op(A) op(B) + beta C for small matrices, one thread per output.
@@ -297,21 +301,41 @@ __global__ void k_finish_r(int k, int KP, const double* __restrict__ Rin, int64_
     }
 }
 
-// prod[c] = Nc[c] (K0P x KP) * G_c (KP x KP, rows of ld ldg starting at row
-// c*k of Gbase; only the first k rows/cols are meaningful), one block per chunk.
-__global__ void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ Nc,
+// prod[c] = N_c G_c (K0P x KP): N_c^T is stored (KP x K0P) in NcT[c]; G_c
+// is KP x KP, rows of ld ldg starting at row c*grow_stride of Gbase (only
+// the first k rows/cols are meaningful).  One block per chunk; both small
+// operands are staged in LDS.
+__global__ void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ NcT,
                              const double* __restrict__ Gbase, int64_t ldg, int64_t grow_stride,
                              double* __restrict__ prod) {
+    __shared__ double Ns[64 * 129];  // N_c^T, KP x (K0P + 1)
+    __shared__ double Gs[64 * 65];   // G_c,   KP x (KP + 1)
     const int c = blockIdx.x;
-    const double* N = Nc + (int64_t)c * K0P * KP;
+    const double* NT = NcT + (int64_t)c * KP * K0P;
     const double* G = Gbase + (int64_t)c * grow_stride * ldg;
     double* out = prod + (int64_t)c * K0P * KP;
+    for (int e = threadIdx.x; e < KP * K0P; e += blockDim.x) Ns[(e / K0P) * (K0P + 1) + e % K0P] = NT[e];
+    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
+        const int i = e / KP, j = e % KP;
+        Gs[i * (KP + 1) + j] = (i < k && j < k) ? G[(int64_t)i * ldg + j] : 0.0;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < K0P * KP; e += blockDim.x) {
         const int i = e / KP, j = e % KP;
         double s = 0.0;
-        if (j < k)
-            for (int p = 0; p < k; p++) s = fma(N[i * KP + p], G[(int64_t)p * ldg + j], s);
+        for (int p = 0; p < k; p++) s = fma(Ns[p * (K0P + 1) + i], Gs[p * (KP + 1) + j], s);
         out[e] = s;
+    }
+}
+
+// dst[(s*CT + ct)*64 + l] = src[((l/16)*(K0P/4) + s)*KP + 16*ct + l%16]: a
+// K0P x KP matrix in the order in which 64 lanes read it as the B operand
+// of FP64 MFMA K-steps whose K index is split as (l/16)*(K0P/4) + s.
+__global__ void k_permute_b(int K0P, int KP, const double* __restrict__ src, double* __restrict__ dst) {
+    const int n = K0P * KP, KS = K0P / 4, CT = KP / 16;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int l = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
+        dst[e] = src[((l >> 4) * KS + s) * KP + 16 * ct + (l & 15)];
     }
 }
 
@@ -391,6 +415,11 @@ hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double
 hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
                            double* G0, hipStream_t st) {
     hipLaunchKernelGGL(k_finish_r, dim3(1), dim3(256), 0, st, k, KP, Rin, ldri, Rout, ldr, G0);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute_b, dim3((K0P * KP + 255) / 256), dim3(256), 0, st, K0P, KP, src, dst);
     return hipGetLastError();
 }
 

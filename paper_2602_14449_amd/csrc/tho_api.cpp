@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
 
 #include "../../include/tho.h"
 #include "tho_internal.h"
@@ -29,6 +30,48 @@ int set_err(int code, const std::string& msg) {
         hipError_t _e = (expr);                                                           \
         if (_e != hipSuccess)                                                             \
             return set_err(THO_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ---- optional per-kernel timing (benchmark instrumentation)
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::vector<std::string> g_prof_names;
+std::vector<double> g_prof_ms;
+std::vector<int64_t> g_prof_cnt;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// Records an event pair around `expr` on stream `st` when profiling is on.
+#define PROF(NAME, st, expr)                                             \
+    do {                                                                 \
+        hipEvent_t _a = nullptr, _b = nullptr;                           \
+        if (g_prof_on) {                                                 \
+            std::lock_guard<std::mutex> _lk(g_prof_mu);                  \
+            _a = prof_event();                                           \
+            _b = prof_event();                                           \
+        }                                                                \
+        if (_a) HIPCHK(hipEventRecord(_a, st));                          \
+        HIPCHK(expr);                                                    \
+        if (_b) {                                                        \
+            HIPCHK(hipEventRecord(_b, st));                              \
+            std::lock_guard<std::mutex> _lk(g_prof_mu);                  \
+            g_prof_pending.push_back({NAME, _a, _b});                    \
+        }                                                                \
     } while (0)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -66,15 +109,16 @@ struct LevelPlan {
 // Chunking of the chunked tall-skinny QR: level 0 gets up to 512 chunks
 // (two per compute unit), upper levels one tile per chunk; every chunk has
 // at least k rows so its first tile can be factored on its own.
-std::vector<LevelPlan> plan_levels(int64_t m0, int k) {
+std::vector<LevelPlan> plan_levels(int64_t m0, int k, int kp) {
     std::vector<LevelPlan> lv;
+    const int tb = tsqr_tile_rows(kp);
     int64_t m = m0;
     for (int level = 0;; level++) {
-        int64_t nc = cdiv(m, LEAF_ROWS);
+        int64_t nc = cdiv(m, tb);
         if (level == 0) nc = std::min<int64_t>(nc, 512);
         nc = std::max<int64_t>(1, std::min<int64_t>(nc, m / std::max(1, k)));
         const int64_t rows_max = cdiv(m, nc);
-        lv.push_back({m, (int)nc, (int)cdiv(rows_max, LEAF_ROWS)});
+        lv.push_back({m, (int)nc, (int)cdiv(rows_max, tb)});
         if (nc == 1) break;
         m = nc * k;
     }
@@ -87,7 +131,7 @@ struct TwoStagePlan {
     int64_t rows_per_blk1;
     std::vector<LevelPlan> lv;
     // workspace pieces
-    double *part, *Cbuf, *Pm, *Tm, *Zbuf, *A1top, *Mbuf, *Nglob, *Rtop, *G0, *Nc, *prod;
+    double *part, *Cbuf, *Pm, *Tm, *Zbuf, *A1top, *Mbuf, *Nglob, *Rtop, *G0, *Nc, *prod, *Zperm, *Nperm;
     std::vector<double*> tau, Tt, stack;  // stack[l] = input matrix of level l (l >= 1)
     size_t bytes;
 };
@@ -96,7 +140,7 @@ void make_plan(int64_t n, int64_t k0, int64_t k, void* ws, TwoStagePlan& P) {
     P.KP = kp_of(k);
     P.K0P = k0p_of(k0);
     const int64_t m0 = n - k0;
-    P.lv = plan_levels(m0, (int)k);
+    P.lv = plan_levels(m0, (int)k, P.KP);
     // phase 1: about 4 workgroups per compute unit, >= 64 rows each
     P.nblk1 = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, 64)));
     P.rows_per_blk1 = cdiv(cdiv(n, P.nblk1), 16) * 16;
@@ -115,9 +159,12 @@ void make_plan(int64_t n, int64_t k0, int64_t k, void* ws, TwoStagePlan& P) {
         P.Mbuf = cv.take(nk);
         P.Nglob = cv.take(nk);
         P.Nc = cv.take((size_t)nc0 * nk);
+        P.Zperm = cv.take(nk);
+        P.Nperm = cv.take(nk);
         P.prod = P.part;
     } else {
         P.part = P.Cbuf = P.Pm = P.Tm = P.Zbuf = P.A1top = P.Mbuf = P.Nglob = P.Nc = P.prod = nullptr;
+        P.Zperm = P.Nperm = nullptr;
     }
     P.Rtop = cv.take(kk);
     P.G0 = cv.take(kk);
@@ -144,6 +191,18 @@ hipError_t fill(double* p, int64_t n, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
+#ifdef THO_DEBUG_SPLIT_VN
+__global__ void k_dbg_add_vn(int64_t m, int k, int k0, const double* V, int64_t ldv, const double* N, int ldn,
+                             double* Q, int64_t ldq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * k) return;
+    const int64_t i = e / k; const int j = (int)(e % k);
+    double s = 0.0;
+    for (int p = 0; p < k0; p++) s += V[i * ldv + p] * N[p * ldn + j];
+    Q[i * ldq + j] += s;
+}
+#endif
+
 int check_common(int32_t dtype, int64_t n, int64_t k0, int64_t k) {
     if (dtype != THO_F64 && dtype != THO_C128) return set_err(-1, "dtype must be THO_F64 or THO_C128");
     if (n < 0) return set_err(-2, "n must be >= 0");
@@ -154,6 +213,17 @@ int check_common(int32_t dtype, int64_t n, int64_t k0, int64_t k) {
 }
 
 }  // namespace
+
+#ifdef THO_DEBUG_SKIP_FORM0
+static size_t g_dbg_tt_off = 0, g_dbg_nc_off = 0, g_dbg_st1_off = 0, g_dbg_ng_off = 0;
+extern "C" size_t tho_debug_nglob(void) { return g_dbg_ng_off; }
+static int64_t g_dbg_m1 = 0;
+static int g_dbg_maxtiles = 0, g_dbg_nchunk = 0;
+extern "C" void tho_debug_offsets(size_t* tt, size_t* nc, int* maxtiles, int* nchunk) {
+    *tt = g_dbg_tt_off; *nc = g_dbg_nc_off; *maxtiles = g_dbg_maxtiles; *nchunk = g_dbg_nchunk;
+}
+extern "C" void tho_debug_stack1(size_t* off, int64_t* m1) { *off = g_dbg_st1_off; *m1 = g_dbg_m1; }
+#endif
 
 extern "C" {
 
@@ -168,6 +238,55 @@ const char* tho_strerror(int code) {
     if (code == THO_E_UNSUPPORTED) return "unsupported combination of arguments";
     if (code < 0) return "invalid argument";
     return "unknown code";
+}
+
+int tho_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return 0;
+}
+
+int tho_profile_collect(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof_pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return set_err(THO_E_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        size_t i = 0;
+        while (i < g_prof_names.size() && g_prof_names[i] != r.name) i++;
+        if (i == g_prof_names.size()) {
+            g_prof_names.push_back(r.name);
+            g_prof_ms.push_back(0.0);
+            g_prof_cnt.push_back(0);
+        }
+        g_prof_ms[i] += ms;
+        g_prof_cnt[i] += 1;
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+    return (int)g_prof_names.size();
+}
+
+int tho_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_names.clear();
+    g_prof_ms.clear();
+    g_prof_cnt.clear();
+    return 0;
+}
+
+int tho_profile_get(int i, char* name, int name_len, double* total_ms, int64_t* launches) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (i < 0 || i >= (int)g_prof_names.size()) return set_err(-1, "profile index out of range");
+    if (name && name_len > 0) {
+        std::strncpy(name, g_prof_names[i].c_str(), (size_t)name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (total_ms) *total_ms = g_prof_ms[i];
+    if (launches) *launches = g_prof_cnt[i];
+    return 0;
 }
 
 int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts,
@@ -222,22 +341,23 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
 
     if (k0 > 0) {
         // line 1, second choice: V_top = Q1 R1, P = -Q1, T = I + R1^T
-        HIPCHK(launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, st));
+        PROF("qr_top", st, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, st));
         // line 4 reduction: C = V^T A over all n rows
-        HIPCHK(launch_xty_partial(mt_of(K0P), KP / 16, n, V, ldv, ik0, A, lda, ik, P.nblk1,
+        PROF("xty_partial", st, launch_xty_partial(mt_of(K0P), KP / 16, n, V, ldv, ik0, A, lda, ik, P.nblk1,
                                   P.rows_per_blk1, P.part, st));
-        HIPCHK(launch_reduce_parts(P.nblk1, (int64_t)K0P * KP, P.part, P.Cbuf, st));
+        PROF("reduce_parts", st, launch_reduce_parts(P.nblk1, (int64_t)K0P * KP, P.part, P.Cbuf, st));
         // W^T A = P^T A_top - C ;  Z = T^{-T} (W^T A)
-        HIPCHK(fill(P.Zbuf, (int64_t)nk, 0.0, st));
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.Cbuf, KP, P.Zbuf,
+        PROF("fill", st, fill(P.Zbuf, (int64_t)nk, 0.0, st));
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.Cbuf, KP, P.Zbuf,
                                  KP, st));
-        HIPCHK(launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Zbuf, KP, st));
+        PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Zbuf, KP, st));
+        PROF("permute", st, launch_permute_b(K0P, KP, P.Zbuf, P.Zperm, st));
         // A1_top = A_top - (P - V_top) Z ;  S = P^T A1_top  (line 5)
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Zbuf, KP, 0, 1.0, A, lda, P.A1top,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Zbuf, KP, 0, 1.0, A, lda, P.A1top,
                                  KP, st));
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Zbuf, KP, 0, 1.0, P.A1top, KP,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Zbuf, KP, 0, 1.0, P.A1top, KP,
                                  P.A1top, KP, st));
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, P.A1top, KP, 0, 0.0, nullptr, 0, S,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, P.A1top, KP, 0, 0.0, nullptr, 0, S,
                                  lds, st));
     }
 
@@ -260,9 +380,9 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
                 L.V = V + k0 * ldv;
                 L.ldv = ldv;
                 L.k0 = ik0;
-                L.Z = P.Zbuf;
+                L.Z = P.Zperm;
                 L.Nc = P.Nc;
-                L.Nglob = P.Nglob;
+                L.Nglob = P.Nperm;
             }
         } else {
             L.X = P.stack[l];
@@ -284,26 +404,46 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
             L.gstride = 0;
         }
     }
-    for (int l = 0; l < nl; l++) HIPCHK(launch_tsqr_leaf(KP, l == 0 ? K0P : 0, Ls[l], st));
+    for (int l = 0; l < nl; l++)
+        PROF(l == 0 ? "leaf_l0" : "leaf_up", st, launch_tsqr_leaf(KP, l == 0 ? K0P : 0, Ls[l], st));
     // R with nonnegative diagonal; the top-level Q starts from the sign matrix
-    HIPCHK(launch_finish_r(ik, KP, P.Rtop, KP, R, ldr, P.G0, st));
-    for (int l = nl - 1; l >= 1; l--) HIPCHK(launch_tsqr_form(KP, 0, Ls[l], st));
+    PROF("finish_r", st, launch_finish_r(ik, KP, P.Rtop, KP, R, ldr, P.G0, st));
+    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(KP, 0, Ls[l], st));
 
     if (k0 > 0) {
         // line 7: G = W^T [0; Q_] = -sum_c N_c G_c ;  N = T^{-1} G
-        HIPCHK(launch_chunk_prod(Ls[0].nchunk, K0P, KP, ik, P.Nc, Ls[0].Gin, Ls[0].ldg, Ls[0].gstride,
+        PROF("chunk_prod", st, launch_chunk_prod(Ls[0].nchunk, K0P, KP, ik, P.Nc, Ls[0].Gin, Ls[0].ldg, Ls[0].gstride,
                                  P.prod, st));
-        HIPCHK(launch_reduce_parts(Ls[0].nchunk, (int64_t)K0P * KP, P.prod, P.Mbuf, st));
-        HIPCHK(launch_small_gemm(K0P, KP, 0, 0.0, P.Mbuf, KP, 0, P.Mbuf, KP, 0, -1.0, P.Mbuf, KP,
+        PROF("reduce_parts", st, launch_reduce_parts(Ls[0].nchunk, (int64_t)K0P * KP, P.prod, P.Mbuf, st));
+        PROF("small_gemm", st, launch_small_gemm(K0P, KP, 0, 0.0, P.Mbuf, KP, 0, P.Mbuf, KP, 0, -1.0, P.Mbuf, KP,
                                  P.Nglob, KP, st));
-        HIPCHK(launch_trsm_lower(ik0, ik, P.Tm, k0, 0, P.Nglob, KP, st));
+        PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 0, P.Nglob, KP, st));
+        PROF("permute", st, launch_permute_b(K0P, KP, P.Nglob, P.Nperm, st));
         // Q_top = -(P - V_top) N
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Nglob, KP, 0, 0.0, nullptr, 0, Q, ldq,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Nglob, KP, 0, 0.0, nullptr, 0, Q, ldq,
                                  st));
-        HIPCHK(launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Nglob, KP, 0, 1.0, Q, ldq, Q, ldq,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Nglob, KP, 0, 1.0, Q, ldq, Q, ldq,
                                  st));
     }
-    HIPCHK(launch_tsqr_form(KP, K0P, Ls[0], st));
+#ifdef THO_DEBUG_SKIP_FORM0
+    g_dbg_st1_off = (nl > 1) ? (size_t)((char*)P.stack[1] - (char*)ws) : 0;
+    g_dbg_ng_off = P.Nglob ? (size_t)((char*)P.Nglob - (char*)ws) : 0;
+    g_dbg_m1 = (nl > 1) ? P.lv[1].m : 0;
+    g_dbg_tt_off = (size_t)((char*)P.Tt[0] - (char*)ws);
+    g_dbg_nc_off = P.Nc ? (size_t)((char*)P.Nc - (char*)ws) : 0;
+    g_dbg_maxtiles = P.lv[0].maxtiles;
+    g_dbg_nchunk = P.lv[0].nchunk;
+    return 0;
+#endif
+#ifdef THO_DEBUG_SPLIT_VN
+    if (k0 > 0) {
+        PROF("form_l0", st, launch_tsqr_form(KP, 0, Ls[0], st));
+        hipLaunchKernelGGL(k_dbg_add_vn, dim3((unsigned)cdiv((n - k0) * k, 256)), dim3(256), 0, st,
+                           n - k0, ik, ik0, V + k0 * ldv, ldv, (const double*)P.Nglob, KP, Q + k0 * ldq, ldq);
+        return 0;
+    }
+#endif
+    PROF("form_l0", st, launch_tsqr_form(KP, K0P, Ls[0], st));
     return 0;
 }
 

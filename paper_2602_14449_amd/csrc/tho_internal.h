@@ -8,10 +8,10 @@
 namespace tho {
 
 // Tile geometry of the tall-skinny Householder kernels: a workgroup of
-// LEAF_WAVES wavefronts owns a tile of LEAF_ROWS rows; each wavefront holds
-// 32 rows (two 16-row MFMA blocks) of the tile in registers.
-constexpr int LEAF_WAVES = 8;
-constexpr int LEAF_ROWS = 256;
+// LEAF_WAVES wavefronts owns a tile of tsqr_tile_rows(kp) rows held in
+// registers (16-row MFMA blocks per wavefront).
+constexpr int LEAF_WAVES = 4;
+int tsqr_tile_rows(int kp);
 
 // Arguments of one level of the chunked tall-skinny QR (leaf) and of the
 // matching Q formation (form).  Level 0 works on the bottom n - k0 rows of A
@@ -31,9 +31,9 @@ struct TsqrLevel {
     const double* V;  // bottom rows of V; ld ldv
     int64_t ldv;
     int k0;
-    const double* Z;  // K0P x KP: the k0 x k solve result of line 4
-    double* Nc;       // per chunk K0P x KP: V_chunk^T Q_chunk (leaf output)
-    const double* Nglob;  // K0P x KP: T^{-1} G (form input)
+    const double* Z;  // K0P x KP Z of line 4, in B-operand order (k_permute_b)
+    double* Nc;       // per chunk KP x K0P: Q_chunk^T V_chunk (leaf output)
+    const double* Nglob;  // K0P x KP N = T^{-1} G, in B-operand order (form input)
     // per-tile storage
     double* tau;      // [nchunk * maxtiles][KP]
     double* Tt;       // [nchunk * maxtiles][KP * KP]
@@ -59,6 +59,7 @@ hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int tra
 hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double* T, hipStream_t st);
 hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
                            double* G0, hipStream_t st);
+hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st);
 hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
                              int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st);
 
