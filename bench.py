@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--cpu-rows", type=int, default=1 << 20)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="launch one plain 1 GiB device copy first (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -112,6 +114,14 @@ def main():
     S = torch.empty(k0, k, dtype=torch.float64, device=dev)
     ws = torch.empty(tho.workspace_bytes(n, k0, k), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
+    if a.copy_calib:
+        # known traffic: 2^30 bytes read + 2^30 bytes written
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)              # runtime copy (hipMemcpy device to device)
+        torch.neg(src, out=dst)     # elementwise kernel, same traffic
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         tho.two_stage(V, A, out=(Q, R, S), workspace=ws)
     torch.cuda.synchronize()
