@@ -44,7 +44,7 @@ extern "C" {
 
 typedef enum { THO_F64 = 0, THO_C128 = 1 } tho_dtype_t;
 
-/* Choice of the unitary P of line 1 of Algorithm 1 (§3.2).  Only the second
+/* Choice of the unitary P of Algorithm 1 (§3.2).  Only the second
  * choice (QR of the top block, P = -Q1, T = I + R1^*) is implemented; it is
  * the one the paper recommends (§6.2, §7). */
 typedef enum { THO_P_QR = 0 } tho_pchoice_t;
@@ -96,6 +96,54 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   const void* V, int64_t ldv, const void* A, int64_t lda,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Block classical Gram-Schmidt, the baseline of eq. (1) and Table 1:
+ * `rounds` rounds, each running `proj` projections
+ *     C = V^T X,  X <- X - V C,  S_r <- S_r + C          (BQR-1)
+ * followed by one Householder QR X = Q_r R_r (BQR-2, the same chunked
+ * Householder QR as tho_two_stage, nonnegative diag R_r).  Round 1 starts
+ * from X = A, later rounds from the previous Q.  Outputs satisfy
+ * A ~ V S + Q R with S = S_1 + S_2 R_1 + S_3 R_2 R_1 + ..., R = R_r ... R_1.
+ * Table 1's rows are (proj, rounds) = (1,1), (2,1), (1,2), (3,1), (1,3).
+ * Arguments 1-14 as tho_two_stage; 15 proj (1..8), 16 rounds (1..8),
+ * 17 opts (panel must be THO_PANEL_F64), 18 ws, 19 ws_bytes, 20 stream.
+ * THO_F64 only (THO_E_UNSUPPORTED otherwise).  Unlike the two-stage method,
+ * the orthogonality of Q is only as good as the conditioning of [V, A]
+ * allows (Table 1): this is the comparison baseline, not a robust method. */
+int tho_bcgs_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, int32_t proj, int32_t rounds,
+                       const tho_opts_t* opts, size_t* bytes);
+int tho_bcgs(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+             const void* V, int64_t ldv, const void* A, int64_t lda,
+             void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
+             int32_t proj, int32_t rounds,
+             const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint (reverse-mode gradient) of the map (V, A) -> (Q, R, S) that
+ * tho_two_stage computes, real FP64.  The paper does not treat
+ * differentiation; this is the exact adjoint of the steps of Algorithm 1
+ * (second choice of P) taken in reverse order, with the thin-QR adjoint
+ * X_bar = (Q_bar + Q copyltu(R R_bar^T - Q_bar^T Q)) R^{-T} for the QR of
+ * the bottom block and for the square QR of V_top.  For a scalar loss l with
+ * gQ = dl/dQ, gR = dl/dR (only its upper triangle is used) and gS = dl/dS,
+ * it returns dV = dl/dV and dA = dl/dA, V and A taken as unconstrained
+ * matrices.  Q and R must be the outputs of tho_two_stage for (V, A); the
+ * WY factors are recomputed from V, A, Q (never stored), using W^T Q = -T^T N
+ * which holds for orthonormal V.
+ * Arguments: 1 dtype (THO_F64), 2 n, 3 k0, 4 k, 5 V, 6 ldv, 7 A, 8 lda,
+ * 9 Q, 10 ldq, 11 R, 12 ldr, 13 gQ (n x k), 14 ldgq, 15 gR (k x k),
+ * 16 ldgr, 17 gS (k0 x k, may be NULL for zero), 18 ldgs, 19 dV (n x k0,
+ * out), 20 lddv, 21 dA (n x k, out), 22 ldda, 23 opts, 24 ws, 25 ws_bytes,
+ * 26 stream.  dV and dA are fully overwritten and must not alias inputs.
+ * R must be nonsingular (the QR adjoint divides by diag R). */
+int tho_two_stage_backward_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts,
+                                     size_t* bytes);
+int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+                           const void* V, int64_t ldv, const void* A, int64_t lda,
+                           const void* Q, int64_t ldq, const void* R, int64_t ldr,
+                           const void* gQ, int64_t ldgq, const void* gR, int64_t ldgr,
+                           const void* gS, int64_t ldgs,
+                           void* dV, int64_t lddv, void* dA, int64_t ldda,
+                           const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Benchmark instrumentation (not needed for normal use).
  * tho_profile_enable(1) makes every later call record a pair of hipEvents on

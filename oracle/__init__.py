@@ -14,7 +14,7 @@ LAPACK QR for very tall inputs, eigenvalues for 2-norms) are used as single
 steps; nothing is blocked, fused or reordered beyond what the paper states.
 
 Modules
-  householder  column Householder QR (the intra-block QR of line 6 of
+  householder  column Householder QR (the intra-block QR of
                Algorithm 1 and the QR of the top block for the second choice
                of P), with the nonnegative-diagonal phase convention
   two_stage    Algorithm 1 with the second choice of P (§3.1, §3.2)

@@ -60,7 +60,7 @@ def two_stage_vjp(V, A, GQ, GR, GS=None):
     Abar = np.zeros((n, k))
     A1bar = np.zeros((n, k))
 
-    # line 7: Q = X - W N, N = T^{-1} G, G = W^T X, X = [0; Q_]
+    # formation of Q: Q = X - W N, N = T^{-1} G, G = W^T X, X = [0; Q_]
     X = np.zeros((n, k))
     X[k0:] = Qu
     Xbar = Qbar.copy()
@@ -75,14 +75,14 @@ def two_stage_vjp(V, A, GQ, GR, GS=None):
     Xbar += W @ Gbar
     Qubar = Xbar[k0:]
 
-    # line 6: A1_low = Q_ R
+    # QR of the bottom block: A1_low = Q_ R
     A1bar[k0:] = qr_adjoint(Qu, R, Qubar, Rbar)
 
-    # line 5: S = P^T A1_top
+    # S = P^T A1_top
     Pbar += A1[:k0] @ Sbar.T
     A1bar[:k0] += P @ Sbar
 
-    # line 4: A1 = A - W Z, Z = T^{-T} Y, Y = W^T A
+    # update of A: A1 = A - W Z, Z = T^{-T} Y, Y = W^T A
     Abar += A1bar
     Wbar -= A1bar @ Z.T
     Zbar = -W.T @ A1bar
@@ -94,11 +94,11 @@ def two_stage_vjp(V, A, GQ, GR, GS=None):
     Wbar += A @ Ybar.T
     Abar += W @ Ybar
 
-    # line 2: W = [P; 0] - V
+    # W = [P; 0] - V
     Vbar = -Wbar
     Pbar += Wbar[:k0]
 
-    # line 1 / 3: P = -Q1, T = I + R1^T, V_top = Q1 R1
+    # choice of P and T: P = -Q1, T = I + R1^T, V_top = Q1 R1
     if k0 > 0:
         R1bar = np.triu(np.tril(Tbar).T)
         Q1bar = -Pbar

@@ -4,7 +4,7 @@ Test infrastructure only (see ``oracle/__init__``).
 
 Paper passages followed
   * The intra-block orthogonalization step is Householder-QR (§1, after
-    eq. (1); line 6 of Algorithm 1).  Householder-QR satisfies Assumption 1
+    eq. (1); the bottom-block QR of Algorithm 1).  Householder-QR satisfies Assumption 1
     (§4; Appendix B.1).
   * The second choice of P needs a QR factorization of the top k0 x k0 block
     of V whose R factor has nonnegative diagonal entries (§3.2, second

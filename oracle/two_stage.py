@@ -12,14 +12,14 @@ Followed passages
     QR of A_low = Q_ R; Q = (I - W T^{-1} W^*) [0; Q_].
   * §3.2, second choice: V_top = Q1 R1 with nonnegative diag(R1), P = -Q1,
     T = I + R1^* (lower triangular).  Appendix B.2 analyses exactly the
-    computed form T = fl(I + R1^*), which is the form used here.  (Line 3 of
-    Algorithm 1 gives T = I - V_top^* P, equal whenever Q1 is unitary; the
+    computed form T = fl(I + R1^*), which is the form used here.  (Algorithm 1 itself
+    writes T = I - V_top^* P, equal whenever Q1 is unitary; the
     tests check the two agree to rounding.)
 
 Readings taken where the paper is silent (listed in the design doc as well)
   * Intra-block QR: column Householder with the nonnegative-diagonal phase
     convention (``householder.qr_pos``).
-  * S is computed exactly as line 5 states, P^* A_top after the update, not
+  * S is computed exactly as Algorithm 1 states, P^* A_top after the update, not
     as V^* A (they agree in exact arithmetic when V^* V = I).
   * n >= k0 + k is required; k0 = 0 reduces to qr_pos(A); k = 0 is a no-op.
 """
@@ -38,7 +38,7 @@ def two_stage_intermediates(V, A, qr_method="auto"):
     """Run Algorithm 1 (second choice of P) and return every intermediate.
 
     Returns a dict with P, T, W, Y (= W^* A), Z (= T^{-*} Y), A1 (updated A),
-    S, Qu (Q_ of line 6), R, G (= W^* [0; Q_]), N (= T^{-1} G) and Q.
+    S, Qu (Q_ of the bottom-block QR), R, G (= W^* [0; Q_]), N (= T^{-1} G) and Q.
     """
     V = np.asarray(V)
     A = np.asarray(A)
@@ -52,35 +52,35 @@ def two_stage_intermediates(V, A, qr_method="auto"):
     if n < k0 + k:
         raise ValueError("need n >= k0 + k")
     out = {}
-    # line 1, second choice (§3.2): V_top = Q1 R1, diag(R1) >= 0, P = -Q1
+    # choice of P, second choice (§3.2): V_top = Q1 R1, diag(R1) >= 0, P = -Q1
     if k0 > 0:
         Q1, R1 = qr_pos(V[:k0, :], method="loop")
     else:
         Q1 = np.zeros((0, 0), dt)
         R1 = np.zeros((0, 0), dt)
     P = -Q1
-    # line 2: W = [P; 0] - V
+    # W = [P; 0] - V
     X0 = np.zeros((n, k0), dt)
     X0[:k0, :] = P
     W = X0 - V
-    # line 3 in the form analysed in Appendix B.2: T = I + R1^* (lower tri.)
+    # T in the form analysed in Appendix B.2: T = I + R1^* (lower tri.)
     T = np.eye(k0, dtype=dt) + _h(R1)
-    # line 4: A <- A - W T^{-*} (W^* A)
+    # update of A: A <- A - W T^{-*} (W^* A)
     Y = _h(W) @ A
     if k0 > 0:
         Z = solve_triangular(_h(T), Y, lower=False)   # T^* is upper triangular
     else:
         Z = np.zeros((0, k), dt)
     A1 = A - W @ Z
-    # line 5: S = P^* A_top
+    # S = P^* A_top
     S = _h(P) @ A1[:k0, :]
-    # line 6: QR of the bottom n - k0 rows
+    # QR of the bottom n - k0 rows
     if k > 0:
         Qu, R = qr_pos(A1[k0:, :], method=qr_method)
     else:
         Qu = np.zeros((n - k0, 0), dt)
         R = np.zeros((0, 0), dt)
-    # line 7: Q = [0; Q_] - W T^{-1} (W^* [0; Q_])
+    # formation of Q: Q = [0; Q_] - W T^{-1} (W^* [0; Q_])
     Xq = np.zeros((n, k), dt)
     Xq[k0:, :] = Qu
     G = _h(W) @ Xq

@@ -43,8 +43,26 @@ tho_two_stage = _proto(
     [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
      c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
 
+tho_bcgs_workspace = _proto(
+    "tho_bcgs_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_i32, c_i32, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_bcgs = _proto(
+    "tho_bcgs", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+     c_i64, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+tho_two_stage_backward_workspace = _proto(
+    "tho_two_stage_backward_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_two_stage_backward = _proto(
+    "tho_two_stage_backward", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+     c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+     ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
-            "tho_two_stage_workspace", "tho_two_stage"]
+            "tho_two_stage_workspace", "tho_two_stage",
+            "tho_bcgs_workspace", "tho_bcgs",
+            "tho_two_stage_backward_workspace", "tho_two_stage_backward"]
 
 THO_F64 = 0
 THO_C128 = 1

@@ -18,7 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtho.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["k_small.hip", "k_tsqr.hip", "tho_api.cpp"]
+SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
+           "tho_backward.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -39,7 +40,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

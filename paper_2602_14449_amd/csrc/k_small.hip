@@ -339,7 +339,34 @@ __global__ void k_permute_b(int K0P, int KP, const double* __restrict__ src, dou
     }
 }
 
+// D = a op(X) + b op(Y) + c I (M x N), masked: mode 1 keeps j <= i, mode 2
+// keeps j >= i, mode 3 mirrors the lower part to the upper (copyltu).
+__global__ void k_small_ew(int M, int N, double a, const double* __restrict__ X, int64_t ldx, int tx, double b,
+                           const double* __restrict__ Y, int64_t ldy, int ty, double c, int mode, double* D,
+                           int64_t ldd) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * N) return;
+    const int i = (int)(t / N), j = (int)(t % N);
+    int si = i, sj = j;
+    if (mode == 3 && j > i) { si = j; sj = i; }
+    double v = 0.0;
+    if (X) v += a * (tx ? X[(int64_t)sj * ldx + si] : X[(int64_t)si * ldx + sj]);
+    if (Y) v += b * (ty ? Y[(int64_t)sj * ldy + si] : Y[(int64_t)si * ldy + sj]);
+    if (si == sj) v += c;
+    if ((mode == 1 && j > i) || (mode == 2 && j < i)) v = 0.0;
+    D[(int64_t)i * ldd + j] = v;
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_small_ew(int M, int N, double a, const double* X, int64_t ldx, int tx, double b, const double* Y,
+                           int64_t ldy, int ty, double c, int mode, double* D, int64_t ldd, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t nb = ((int64_t)M * N + 255) / 256;
+    hipLaunchKernelGGL(k_small_ew, dim3((unsigned)nb), dim3(256), 0, st, M, N, a, X, ldx, tx, b, Y, ldy, ty, c, mode,
+                       D, ldd);
+    return hipGetLastError();
+}
 
 #define XTY_CASE(MT, NT, WM)                                                               \
     if (mt == MT && nt == NT) {                                                             \

@@ -1,5 +1,5 @@
-// Chunked tall-skinny Householder QR (the intra-block QR of line 6 of
-// Algorithm 1) and the explicit formation of Q (line 7), for gfx950.
+// Chunked tall-skinny Householder QR (the QR of the bottom block in
+// Algorithm 1) and the explicit formation of Q, for gfx950.
 //
 // Structure.  The m x k matrix is split into `nchunk` row chunks, one
 // workgroup each.  A workgroup walks its chunk in tiles of 128 or 256 rows and keeps
@@ -14,9 +14,9 @@
 //
 // Level 0 (the bottom n - k0 rows of A) is fused with the generalized
 // Householder step of Algorithm 1: the tile loaded from A is updated to
-// A + V Z on MFMA before factorization (line 4), and the chunk accumulates
+// A + V Z on MFMA before factorization (the update of A), and the chunk accumulates
 // N_c = V_chunk^T Q_chunk, which gives W^T [0; Q_] = -sum_c N_c G_c without
-// another pass over V (line 7).
+// another pass over V (formation of Q).
 //
 // Register tile: 4 wavefronts x 32 or 64 rows; each wavefront keeps two or
 // four 16 x KP row blocks in FP64 MFMA accumulator layout (tho_device.h), so the
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
                     }
         }
 
-        // ---- line 4 of Algorithm 1 on these rows: A <- A + V Z  (MFMA; Z is
+        // ---- the update of A (Algorithm 1) on these rows: A <- A + V Z  (MFMA; Z is
         // read in B-operand order from L.Z, see k_permute_b)
         if (HASV && k0 > 0) {
             const int l = opaque_lane(), g = l >> 4, cl = l & 15;
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
 // C carries G_c down the flat tree:
 //   structured tile t:  K = T_t C,                rows = -Y_t K,  C <- C - K
 //   plain tile 0:       K = T_0 (Y_0[0:k]^T C),   rows = [C; 0] - Y_0 K
-// Level 0 adds V N (line 7 of Algorithm 1: Q_low = Q_ + V_low N).
+// Level 0 adds V N (formation of Q in Algorithm 1: Q_low = Q_ + V_low N).
 // Output rows overwrite the Householder vectors in place.
 template <int KP, int K0P>
 __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {

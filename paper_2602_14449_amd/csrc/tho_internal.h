@@ -31,7 +31,7 @@ struct TsqrLevel {
     const double* V;  // bottom rows of V; ld ldv
     int64_t ldv;
     int k0;
-    const double* Z;  // K0P x KP Z of line 4, in B-operand order (k_permute_b)
+    const double* Z;  // K0P x KP Z of the update of A, in B-operand order (k_permute_b)
     double* Nc;       // per chunk KP x K0P: Q_chunk^T V_chunk (leaf output)
     const double* Nglob;  // K0P x KP N = T^{-1} G, in B-operand order (form input)
     // per-tile storage
@@ -62,6 +62,44 @@ hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, doubl
 hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st);
 hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
                              int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st);
+
+// Elementwise small-matrix helper (M x N):
+//   D = a op(X) + b op(Y) + c I, then masked by `mode`
+// op(.) transposes when tx / ty; mode 0 none, 1 lower (j <= i kept),
+// 2 upper (j >= i kept), 3 copyltu (lower part mirrored to the upper).
+// X or Y may be null (term skipped).  D must not alias X or Y when a
+// transpose or mode 3 is used.
+hipError_t launch_small_ew(int M, int N, double a, const double* X, int64_t ldx, int tx, double b, const double* Y,
+                           int64_t ldy, int ty, double c, int mode, double* D, int64_t ldd, hipStream_t st);
+
+// Row-streaming panel product Out = X + sum_t Y_t B_t (k_stream.hip).
+// X may be NULL (taken as 0) and may alias Out; q <= 128 output columns;
+// each B_t is p_t x q packed by launch_pack_b with kpad_t (multiple of 16,
+// >= p_t) rows and rows_gemm_qp(q) columns.
+struct RowsTerm {
+    const double* Y;
+    int64_t ldy;
+    int p;
+    int kpad;
+    const double* B;
+};
+struct RowsGemm {
+    static constexpr int MAXT = 4;
+    int64_t nrows;
+    const double* X;
+    int64_t ldx;
+    double* Out;
+    int64_t ldo;
+    int q;
+    int nterm;
+    RowsTerm t[MAXT];
+};
+int rows_gemm_qp(int q);
+hipError_t launch_rows_gemm(const RowsGemm& g, hipStream_t st);
+// dst = scale * op(src) (p x q; op = transpose if trans) in B-operand order,
+// zero padded to kpad x qp.
+hipError_t launch_pack_b(int p, int q, const double* src, int64_t lds, int trans, double scale, int kpad, int qp,
+                         double* dst, hipStream_t st);
 
 // kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term)
 hipError_t launch_tsqr_leaf(int kp, int k0p, const TsqrLevel& L, hipStream_t st);

@@ -1,0 +1,84 @@
+"""GPU parity of the BCGS baseline (tho_bcgs) against the CPU oracle.
+
+eq. (1) with the repetition patterns of Table 1: element-wise against the
+oracle's bcgs on well-conditioned inputs (all patterns agree there to
+rounding), and the Table 1 loss pattern on the eq. (2) matrices.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import tho_workloads as W
+from oracle import bcgs as oracle_bcgs, orth_loss, rel_residual
+
+from gpu_util import require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+PATTERNS = [(1, 1), (2, 1), (1, 2), (3, 1), (1, 3)]
+
+
+def _run(V, A, proj, rounds):
+    import paper_2602_14449_amd as tho
+    Q, R, S = tho.bcgs(to_dev(V), to_dev(A), proj, rounds)
+    return to_host(Q), to_host(R), to_host(S)
+
+
+@pytest.mark.parametrize("proj,rounds", PATTERNS)
+@pytest.mark.parametrize("n,k0,k", [(4096, 16, 8), (50_000, 64, 32), (9999, 100, 50), (3000, 0, 12)])
+def test_bcgs_parity(n, k0, k, proj, rounds):
+    require_gpu()
+    g = np.random.default_rng(500 + n + k0 + k)
+    V = W.orthonormal(g, n, k0)
+    A = g.standard_normal((n, k))
+    Qg, Rg, Sg = _run(V, A, proj, rounds)
+    Qo, Ro, So = oracle_bcgs(V, A, proj=proj, rounds=rounds)
+    assert np.abs(Qg - Qo).max() < 1e-10
+    assert np.abs(Rg - Ro).max() < 1e-10 * max(1.0, np.abs(Ro).max())
+    if k0:
+        assert np.abs(Sg - So).max() < 1e-10 * max(1.0, np.abs(So).max())
+    assert orth_loss(V, Qg) < 1e-12
+    assert rel_residual(V, A, Qg, Rg, Sg) < 1e-12
+
+
+def test_bcgs_table1_pattern():
+    # Table 1 on the eq. (2) matrices: one projection and one QR loses
+    # orthogonality completely, three projections or three rounds reach
+    # rounding level.  The partial losses printed for (2,1) and (1,2)
+    # (9.8e-2, 7.0e-2) are set by the rounding order of the 1e-30-scaled
+    # products (MATLAB's); fused multiply-adds on the GPU round differently,
+    # so for those rows only boundedness is checked and the value printed.
+    require_gpu()
+    here = os.path.dirname(os.path.abspath(__file__))
+    gold = json.load(open(os.path.join(here, "golden", "table1_bcgs.json")))
+    V, A = W.example2()
+    for row in gold["rows"]:
+        Q, R, S = _run(V, A, row["proj"], row["rounds"])
+        loss = orth_loss(V, Q)
+        print(row["procedure"], "printed", row["printed"], "gpu", loss)
+        if row["printed"] >= 0.5:
+            assert loss >= 0.5
+        elif row["printed"] > 1e-10:
+            assert loss < 1.5
+        else:
+            assert loss < 1e-14
+        assert rel_residual(V, A, Q, R, S) < 1e-14
+
+
+def test_bcgs_ill_conditioned_complex_pattern_real_analogue():
+    # A = V C + 1e-10 G (cond([V, A]) ~ 1e10): one projection loses about
+    # u * cond of orthogonality, a second round restores it
+    require_gpu()
+    g = np.random.default_rng(9)
+    n, k0, k = 1 << 16, 64, 32
+    V = W.orthonormal(g, n, k0)
+    A = V @ g.standard_normal((k0, k)) + 1e-10 * g.standard_normal((n, k))
+    Q1, _, _ = _run(V, A, 1, 1)
+    Q2, _, _ = _run(V, A, 1, 2)
+    l1, l2 = orth_loss(V, Q1), orth_loss(V, Q2)
+    print("BCGS(1,1)", l1, "BCGS(1,2)", l2)
+    assert l1 > 1e-9
+    assert l2 < 1e-13

@@ -138,7 +138,7 @@ def test_second_choice_identities(cplx):
     Ti = np.linalg.inv(T)
     assert np.max(np.abs(Ti)) <= 2 + 1e-12                    # |(T^-1)_ij| <= 2
     assert np.linalg.cond(T) < 2 * np.sqrt(2) * k0            # kappa(T) < 2 sqrt2 k0
-    # line 3 of Algorithm 1 versus the Appendix B.2 form
+    # T as written in Algorithm 1 versus the Appendix B.2 form
     T_line3 = np.eye(k0) - np.conj(V[:k0]).T @ P
     assert np.linalg.norm(T - T_line3, 2) < 1e-14
 
@@ -156,7 +156,7 @@ def test_theorem1_dense_H():
     assert np.linalg.norm(H @ X - V, 2) < 1e-14               # H X = Y
     assert np.linalg.norm(H.T @ H - np.eye(n), 2) < 1e-14     # unitary
     assert np.linalg.norm(H.T @ V - X, 2) < 1e-14             # H^* Y = X
-    # line 4 equals H^* A, line 7 equals H [0; Q_]
+    # the update of A equals H^* A, the formation of Q equals H [0; Q_]
     assert np.allclose(o["A1"], H.T @ A, atol=1e-13)
     Xq = np.zeros((n, k))
     Xq[k0:] = o["Qu"]
