@@ -97,6 +97,22 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* Householder QR of the whole matrix [V, A] (the baseline the method is
+ * compared with in §6: V's columns are factored too, nothing assumes V is
+ * orthonormal).  Computed as the block Householder QR of Algorithm 4 over
+ * column panels of at most 64: the first panel of V by the chunked
+ * Householder QR, every later panel (the rest of V, then A) by the
+ * generalized Householder step of Algorithm 1 against the computed Q of the
+ * earlier panels.  With [V, A] = Q_B R_B (nonnegative diag R_B) it returns
+ * Q = Q_B[:, k0:], R = R_B[k0:, k0:], S = R_B[:k0, k0:] -- the layout of
+ * eq. (4).  Arguments as tho_two_stage; THO_F64 only.  The workspace holds
+ * the n x k0 basis of V's panels. */
+int tho_hhqr_full_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts, size_t* bytes);
+int tho_hhqr_full(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+                  const void* V, int64_t ldv, const void* A, int64_t lda,
+                  void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
+                  const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* Block classical Gram-Schmidt, the baseline of eq. (1) and Table 1:
  * `rounds` rounds, each running `proj` projections
  *     C = V^T X,  X <- X - V C,  S_r <- S_r + C          (BQR-1)

@@ -43,6 +43,13 @@ tho_two_stage = _proto(
     [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
      c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
 
+tho_hhqr_full_workspace = _proto(
+    "tho_hhqr_full_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_hhqr_full = _proto(
+    "tho_hhqr_full", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+     c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
 tho_bcgs_workspace = _proto(
     "tho_bcgs_workspace", ctypes.c_int,
     [c_i32, c_i64, c_i64, c_i64, c_i32, c_i32, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
@@ -61,6 +68,7 @@ tho_two_stage_backward = _proto(
 
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
             "tho_two_stage_workspace", "tho_two_stage",
+            "tho_hhqr_full_workspace", "tho_hhqr_full",
             "tho_bcgs_workspace", "tho_bcgs",
             "tho_two_stage_backward_workspace", "tho_two_stage_backward"]
 

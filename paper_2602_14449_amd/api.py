@@ -93,6 +93,34 @@ def two_stage(V, A, *, panel="fp64", out=None, workspace=None):
     return Q, R, S
 
 
+def hhqr_full(V, A, *, out=None, workspace=None):
+    """Householder QR of [V, A] (block Householder over 64-column panels):
+    returns (Q, R, S) = (Q_B[:, k0:], R_B[k0:, k0:], R_B[:k0, k0:])."""
+    code, n, k0, k = _check_inputs(V, A)
+    Q, R, S = _outputs(out, n, k0, k, A)
+    o = _opts()
+    nb = L.c_sz(0)
+    L.check(L.tho_hhqr_full_workspace(code, n, k0, k, ctypes.byref(o), ctypes.byref(nb)),
+            "tho_hhqr_full_workspace")
+    workspace = _workspace(nb.value, workspace, A.device)
+    rc = L.tho_hhqr_full(code, n, k0, k,
+                         _ptr(V), _ld(V, "V"), A.data_ptr(), _ld(A, "A"),
+                         Q.data_ptr(), _ld(Q, "Q"), R.data_ptr(), _ld(R, "R"),
+                         _ptr(S), _ld(S, "S") if k0 > 0 else max(k, 1),
+                         ctypes.byref(o), workspace.data_ptr(), workspace.numel(),
+                         _stream(A.device))
+    L.check(rc, "tho_hhqr_full")
+    return Q, R, S
+
+
+def hhqr_full_workspace_bytes(n, k0, k):
+    nb = L.c_sz(0)
+    o = _opts()
+    L.check(L.tho_hhqr_full_workspace(L.THO_F64, n, k0, k, ctypes.byref(o), ctypes.byref(nb)),
+            "tho_hhqr_full_workspace")
+    return nb.value
+
+
 def bcgs(V, A, proj=1, rounds=1, *, out=None, workspace=None):
     """Block classical Gram-Schmidt baseline (eq. (1), Table 1 patterns):
     returns (Q, R, S) with A ~ V S + Q R."""

@@ -76,64 +76,16 @@ int check_io(int64_t k0, int64_t k, const void* V, int64_t ldv, const void* A, i
 }
 }  // namespace tho
 
-extern "C" {
+namespace {
 
-const char* tho_version(void) { return "tho 0.1.0 (gfx950)"; }
-
-const char* tho_last_error(void) { return last_error(); }
-
-const char* tho_strerror(int code) {
-    if (code == 0) return "success";
-    if (code == THO_E_WORKSPACE) return "workspace too small";
-    if (code == THO_E_HIP) return "HIP runtime error";
-    if (code == THO_E_UNSUPPORTED) return "unsupported combination of arguments";
-    if (code < 0) return "invalid argument";
-    return "unknown code";
-}
-
-int tho_profile_enable(int on) { return prof_enable(on); }
-int tho_profile_collect(void) { return prof_collect(); }
-int tho_profile_reset(void) { return prof_reset(); }
-int tho_profile_get(int i, char* name, int name_len, double* total_ms, int64_t* launches) {
-    return prof_get(i, name, name_len, total_ms, launches);
-}
-
-int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts,
-                            size_t* bytes) {
-    int rc = check_common(dtype, n, k0, k);
-    if (rc) return rc;
-    if (!bytes) return set_err(-6, "bytes must not be NULL");
-    (void)opts;
-    if (k == 0) { *bytes = 0; return 0; }
+// Launch sequence of Algorithm 1 (second choice of P) on validated
+// arguments; ws holds at least two_stage_bytes(n, k0, k).
+int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv, const double* A, int64_t lda,
+                  double* Q, int64_t ldq, double* R, int64_t ldr, double* S, int64_t lds, void* ws,
+                  hipStream_t st) {
+    int rc = 0;
     TwoStagePlan P;
-    make_plan(n, k0, k, nullptr, P);
-    *bytes = P.bytes;
-    return 0;
-}
-
-int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V_, int64_t ldv,
-                  const void* A_, int64_t lda, void* Q_, int64_t ldq, void* R_, int64_t ldr, void* S_,
-                  int64_t lds, const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
-    int rc = check_common(dtype, n, k0, k);
-    if (rc) return rc;
-    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented");
-    if (opts && (opts->p_choice != THO_P_QR || opts->panel != THO_PANEL_F64 || opts->flags != 0))
-        return set_err(THO_E_UNSUPPORTED, "only p_choice=THO_P_QR, panel=THO_PANEL_F64 are implemented");
-    if (k == 0) return 0;
-    rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds);
-    if (rc) return rc;
-    if (!ws) return set_err(-16, "workspace is NULL");
-    TwoStagePlan P;
-    make_plan(n, k0, k, nullptr, P);
-    if (ws_bytes < P.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");
     make_plan(n, k0, k, ws, P);
-
-    hipStream_t st = (hipStream_t)stream;
-    const double* V = (const double*)V_;
-    const double* A = (const double*)A_;
-    double* Q = (double*)Q_;
-    double* R = (double*)R_;
-    double* S = (double*)S_;
     const int KP = P.KP, K0P = P.K0P;
     const int ik = (int)k, ik0 = (int)k0;
     const size_t nk = (size_t)std::max(K0P, 16) * KP;
@@ -188,6 +140,130 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
                                  st));
     }
     return tsqr_form0(P.ts, Ls, K0P, st);
+}
+
+size_t two_stage_bytes(int64_t n, int64_t k0, int64_t k) {
+    if (k == 0) return 0;
+    TwoStagePlan P;
+    make_plan(n, k0, k, nullptr, P);
+    return P.bytes;
+}
+
+// Block Householder QR of [V, A] (Algorithm 4 over column panels of at most
+// 64): the first panel by the chunked Householder QR, every later panel
+// against the computed basis of the earlier ones by the generalized
+// Householder step of Algorithm 1; A is the last panel.
+struct HhqrPlan {
+    double *Qv, *Rtmp, *Stmp;
+    void* sub;
+    size_t bytes;
+};
+
+void make_hhqr_plan(int64_t n, int64_t k0, int64_t k, void* ws, HhqrPlan& H) {
+    Carve cv(ws);
+    H.Qv = cv.take((size_t)n * std::max<int64_t>(k0, 1));
+    H.Rtmp = cv.take(64 * 64);
+    H.Stmp = cv.take((size_t)std::max<int64_t>(k0, 1) * 64);
+    size_t sub = two_stage_bytes(n, k0, k);
+    for (int64_t c = 0; c < k0; c += 64) sub = std::max(sub, two_stage_bytes(n, c, std::min<int64_t>(64, k0 - c)));
+    H.sub = cv.take(sub / sizeof(double) + 1);
+    H.bytes = cv.bytes();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tho_version(void) { return "tho 0.1.0 (gfx950)"; }
+
+const char* tho_last_error(void) { return last_error(); }
+
+const char* tho_strerror(int code) {
+    if (code == 0) return "success";
+    if (code == THO_E_WORKSPACE) return "workspace too small";
+    if (code == THO_E_HIP) return "HIP runtime error";
+    if (code == THO_E_UNSUPPORTED) return "unsupported combination of arguments";
+    if (code < 0) return "invalid argument";
+    return "unknown code";
+}
+
+int tho_profile_enable(int on) { return prof_enable(on); }
+int tho_profile_collect(void) { return prof_collect(); }
+int tho_profile_reset(void) { return prof_reset(); }
+int tho_profile_get(int i, char* name, int name_len, double* total_ms, int64_t* launches) {
+    return prof_get(i, name, name_len, total_ms, launches);
+}
+
+int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts,
+                            size_t* bytes) {
+    int rc = check_common(dtype, n, k0, k);
+    if (rc) return rc;
+    if (!bytes) return set_err(-6, "bytes must not be NULL");
+    (void)opts;
+    if (k == 0) { *bytes = 0; return 0; }
+    TwoStagePlan P;
+    make_plan(n, k0, k, nullptr, P);
+    *bytes = P.bytes;
+    return 0;
+}
+
+int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V_, int64_t ldv,
+                  const void* A_, int64_t lda, void* Q_, int64_t ldq, void* R_, int64_t ldr, void* S_,
+                  int64_t lds, const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(dtype, n, k0, k);
+    if (rc) return rc;
+    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented");
+    if (opts && (opts->p_choice != THO_P_QR || opts->panel != THO_PANEL_F64 || opts->flags != 0))
+        return set_err(THO_E_UNSUPPORTED, "only p_choice=THO_P_QR, panel=THO_PANEL_F64 are implemented");
+    if (k == 0) return 0;
+    rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds);
+    if (rc) return rc;
+    if (!ws) return set_err(-16, "workspace is NULL");
+    TwoStagePlan P;
+    make_plan(n, k0, k, nullptr, P);
+    if (ws_bytes < P.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");
+    return run_two_stage(n, k0, k, (const double*)V_, ldv, (const double*)A_, lda, (double*)Q_, ldq, (double*)R_, ldr,
+                         (double*)S_, lds, ws, (hipStream_t)stream);
+}
+
+int tho_hhqr_full_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts, size_t* bytes) {
+    int rc = check_common(dtype, n, k0, k);
+    if (rc) return rc;
+    if (!bytes) return set_err(-6, "bytes must not be NULL");
+    (void)opts;
+    if (k == 0) { *bytes = 0; return 0; }
+    HhqrPlan H;
+    make_hhqr_plan(n, k0, k, nullptr, H);
+    *bytes = H.bytes;
+    return 0;
+}
+
+int tho_hhqr_full(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V_, int64_t ldv, const void* A_,
+                  int64_t lda, void* Q_, int64_t ldq, void* R_, int64_t ldr, void* S_, int64_t lds,
+                  const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(dtype, n, k0, k);
+    if (rc) return rc;
+    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented for tho_hhqr_full");
+    if (opts && (opts->panel != THO_PANEL_F64 || opts->flags != 0))
+        return set_err(THO_E_UNSUPPORTED, "tho_hhqr_full supports panel=THO_PANEL_F64 only");
+    if (k == 0) return 0;
+    if ((rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds))) return rc;
+    if (!ws) return set_err(-16, "workspace is NULL");
+    HhqrPlan H;
+    make_hhqr_plan(n, k0, k, nullptr, H);
+    if (ws_bytes < H.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");
+    make_hhqr_plan(n, k0, k, ws, H);
+    hipStream_t st = (hipStream_t)stream;
+    const double* V = (const double*)V_;
+    // panels of V: Q_B[:, c:c+w] and R_B[c:c+w, c:c+w] (R_B's V block is not returned)
+    for (int64_t c = 0; c < k0; c += 64) {
+        const int64_t w = std::min<int64_t>(64, k0 - c);
+        rc = run_two_stage(n, c, w, H.Qv, k0, V + c, ldv, H.Qv + c, k0, H.Rtmp, 64, H.Stmp, 64, H.sub, st);
+        if (rc) return rc;
+    }
+    // last panel A: Q = Q_B[:, k0:], R = R_B[k0:, k0:], S = R_B[:k0, k0:]
+    return run_two_stage(n, k0, k, H.Qv, k0, (const double*)A_, lda, (double*)Q_, ldq, (double*)R_, ldr, (double*)S_,
+                         lds, H.sub, st);
 }
 
 }  // extern "C"
