@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtho.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
+SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "k_lowp.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
            "tho_backward.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -25,6 +25,7 @@
 // directly an MFMA operand for products that contract over rows.
 #include "tho_device.h"
 #include "tho_internal.h"
+#include "tho_lowp.h"
 
 namespace tho {
 
@@ -212,7 +213,7 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[Geo<KP>::RB][KP / 16]
 
 }  // namespace
 
-template <int KP, int K0P>
+template <int KP, int K0P, int PANEL>
 __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
     constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
     constexpr int CT = KP / 16;
@@ -272,7 +273,9 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
 
         // ---- the update of A (Algorithm 1) on these rows: A <- A + V Z  (MFMA; Z is
         // read in B-operand order from L.Z, see k_permute_b)
-        if (HASV && k0 > 0) {
+        if (PANEL != PANEL_F64 && HASV && k0 > 0) {
+            vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(x, Vt, ldv, RPW * w, trows, k0, L.Zlp, opaque_lane());
+        } else if (HASV && k0 > 0) {
             const int l = opaque_lane(), g = l >> 4, cl = l & 15;
             constexpr int SC = 4;  // K-steps per chunk
 #pragma unroll 2
@@ -497,7 +500,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
 //   plain tile 0:       K = T_0 (Y_0[0:k]^T C),   rows = [C; 0] - Y_0 K
 // Level 0 adds V N (formation of Q in Algorithm 1: Q_low = Q_ + V_low N).
 // Output rows overwrite the Householder vectors in place.
-template <int KP, int K0P>
+template <int KP, int K0P, int PANEL>
 __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
     constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
     constexpr int CT = KP / 16;
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
                     for (int ct = 0; ct < CT; ct++)
                         acc[rb][ct] = mfma(a[s], Kp[(s * CT + ct) * 64 + l], acc[rb][ct]);
             }
-            if (HASV && k0 > 0) {
+            if (PANEL == PANEL_F64 && HASV && k0 > 0) {
                 const double* vp = Vt + yr * ldv + g * KS0;
                 constexpr int HS = (KS0 > 16) ? 16 : KS0;
 #pragma unroll
@@ -641,6 +644,8 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
                 }
             }
         }
+        if (PANEL != PANEL_F64 && HASV && k0 > 0)
+            vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(acc, Vt, ldv, RPW * w, trows, k0, L.Nlp, l);
 #pragma unroll
         for (int rb = 0; rb < RB; rb++)
 #pragma unroll
@@ -656,51 +661,69 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
 
 // ---------------------------------------------------------------- launchers
 
-template <int KP, int K0P>
+template <int KP, int K0P, int PANEL>
 static hipError_t leaf_t(const TsqrLevel& L, hipStream_t st) {
     const size_t shm = LeafLds<KP, K0P>::total * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_leaf<KP, K0P>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_leaf<KP, K0P, PANEL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_tsqr_leaf<KP, K0P>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
+    hipLaunchKernelGGL((k_tsqr_leaf<KP, K0P, PANEL>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
     return hipGetLastError();
 }
 
-template <int KP, int K0P>
+template <int KP, int K0P, int PANEL>
 static hipError_t form_t(const TsqrLevel& L, hipStream_t st) {
     const size_t shm = FormLds<KP, K0P>::total * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_form<KP, K0P>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_form<KP, K0P, PANEL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_tsqr_form<KP, K0P>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
+    hipLaunchKernelGGL((k_tsqr_form<KP, K0P, PANEL>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
     return hipGetLastError();
 }
 
 #define TSQR_DISPATCH(FN)                                  \
     switch (kp * 1000 + k0p) {                             \
-        case 16000: return FN<16, 0>(L, st);               \
-        case 16016: return FN<16, 16>(L, st);              \
-        case 16032: return FN<16, 32>(L, st);              \
-        case 16064: return FN<16, 64>(L, st);              \
-        case 16128: return FN<16, 128>(L, st);             \
-        case 32000: return FN<32, 0>(L, st);               \
-        case 32016: return FN<32, 16>(L, st);              \
-        case 32032: return FN<32, 32>(L, st);              \
-        case 32064: return FN<32, 64>(L, st);              \
-        case 32128: return FN<32, 128>(L, st);             \
-        case 64000: return FN<64, 0>(L, st);               \
-        case 64016: return FN<64, 16>(L, st);              \
-        case 64032: return FN<64, 32>(L, st);              \
-        case 64064: return FN<64, 64>(L, st);              \
-        case 64128: return FN<64, 128>(L, st);             \
+        case 16000: return FN<16, 0, 0>(L, st);            \
+        case 16016: return FN<16, 16, 0>(L, st);           \
+        case 16032: return FN<16, 32, 0>(L, st);           \
+        case 16064: return FN<16, 64, 0>(L, st);           \
+        case 16128: return FN<16, 128, 0>(L, st);          \
+        case 32000: return FN<32, 0, 0>(L, st);            \
+        case 32016: return FN<32, 16, 0>(L, st);           \
+        case 32032: return FN<32, 32, 0>(L, st);           \
+        case 32064: return FN<32, 64, 0>(L, st);           \
+        case 32128: return FN<32, 128, 0>(L, st);          \
+        case 64000: return FN<64, 0, 0>(L, st);            \
+        case 64016: return FN<64, 16, 0>(L, st);           \
+        case 64032: return FN<64, 32, 0>(L, st);           \
+        case 64064: return FN<64, 64, 0>(L, st);           \
+        case 64128: return FN<64, 128, 0>(L, st);          \
+        default: return hipErrorInvalidValue;              \
+    }
+
+// reduced-precision panels exist only with a V term (k0p > 0)
+#define TSQR_DISPATCH_LOWP(FN, P)                          \
+    switch (kp * 1000 + k0p) {                             \
+        case 16016: return FN<16, 16, P>(L, st);           \
+        case 16032: return FN<16, 32, P>(L, st);           \
+        case 16064: return FN<16, 64, P>(L, st);           \
+        case 16128: return FN<16, 128, P>(L, st);          \
+        case 32016: return FN<32, 16, P>(L, st);           \
+        case 32032: return FN<32, 32, P>(L, st);           \
+        case 32064: return FN<32, 64, P>(L, st);           \
+        case 32128: return FN<32, 128, P>(L, st);          \
+        case 64016: return FN<64, 16, P>(L, st);           \
+        case 64032: return FN<64, 32, P>(L, st);           \
+        case 64064: return FN<64, 64, P>(L, st);           \
+        case 64128: return FN<64, 128, P>(L, st);          \
         default: return hipErrorInvalidValue;              \
     }
 
@@ -714,11 +737,15 @@ int tsqr_tile_rows(int kp) {
     return kp >= 64 ? Geo<64>::TB : Geo<16>::TB;
 }
 
-hipError_t launch_tsqr_leaf(int kp, int k0p, const TsqrLevel& L, hipStream_t st) {
+hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st) {
+    if (panel == PANEL_F32X2) TSQR_DISPATCH_LOWP(leaf_t, PANEL_F32X2)
+    if (panel == PANEL_BF16) TSQR_DISPATCH_LOWP(leaf_t, PANEL_BF16)
     TSQR_DISPATCH(leaf_t)
 }
 
-hipError_t launch_tsqr_form(int kp, int k0p, const TsqrLevel& L, hipStream_t st) {
+hipError_t launch_tsqr_form(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st) {
+    if (panel == PANEL_F32X2) TSQR_DISPATCH_LOWP(form_t, PANEL_F32X2)
+    if (panel == PANEL_BF16) TSQR_DISPATCH_LOWP(form_t, PANEL_BF16)
     TSQR_DISPATCH(form_t)
 }
 

@@ -15,10 +15,11 @@ struct TwoStagePlan {
     XtyPlan xp;
     TsqrPlan ts;
     double *part, *Cbuf, *Pm, *Tm, *Zbuf, *A1top, *Mbuf, *Nglob, *Nc, *prod, *Zperm, *Nperm;
+    double *Zlp, *Nlp;  // reduced-precision panels only
     size_t bytes;
 };
 
-void make_plan(int64_t n, int64_t k0, int64_t k, void* ws, TwoStagePlan& P) {
+void make_plan(int64_t n, int64_t k0, int64_t k, void* ws, TwoStagePlan& P, int panel = 0) {
     Carve cv(ws);
     P.KP = kp_of(k);
     P.K0P = k0p_of(k0);
@@ -39,9 +40,15 @@ void make_plan(int64_t n, int64_t k0, int64_t k, void* ws, TwoStagePlan& P) {
         P.Zperm = cv.take(nk);
         P.Nperm = cv.take(nk);
         P.prod = P.part;
+        P.Zlp = P.Nlp = nullptr;
+        if (panel != 0) {
+            const size_t lb = lowp_pack_bytes(panel, P.K0P, P.KP) / sizeof(double) + 1;
+            P.Zlp = cv.take(lb);
+            P.Nlp = cv.take(lb);
+        }
     } else {
         P.part = P.Cbuf = P.Pm = P.Tm = P.Zbuf = P.A1top = P.Mbuf = P.Nglob = P.Nc = P.prod = nullptr;
-        P.Zperm = P.Nperm = nullptr;
+        P.Zperm = P.Nperm = P.Zlp = P.Nlp = nullptr;
     }
     P.bytes = cv.bytes();
 }
@@ -82,10 +89,11 @@ namespace {
 // arguments; ws holds at least two_stage_bytes(n, k0, k).
 int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv, const double* A, int64_t lda,
                   double* Q, int64_t ldq, double* R, int64_t ldr, double* S, int64_t lds, void* ws,
-                  hipStream_t st) {
+                  hipStream_t st, int panel = 0) {
     int rc = 0;
+    if (k0 == 0) panel = 0;
     TwoStagePlan P;
-    make_plan(n, k0, k, ws, P);
+    make_plan(n, k0, k, ws, P, panel);
     const int KP = P.KP, K0P = P.K0P;
     const int ik = (int)k, ik0 = (int)k0;
     const size_t nk = (size_t)std::max(K0P, 16) * KP;
@@ -94,7 +102,7 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
         // P and T, second choice (§3.2): V_top = Q1 R1, P = -Q1, T = I + R1^T
         PROF("qr_top", st, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, st));
         // update of A, reduction: C = V^T A over all n rows
-        rc = xty(P.xp, n, V, ldv, ik0, A, lda, ik, P.part, P.Cbuf, st, "xty_partial");
+        rc = xty(P.xp, n, V, ldv, ik0, A, lda, ik, P.part, P.Cbuf, st, "xty_partial", panel);
         if (rc) return rc;
         // W^T A = P^T A_top - C ;  Z = T^{-T} (W^T A)
         PROF("fill", st, fill(P.Zbuf, (int64_t)nk, 0.0, st));
@@ -102,6 +110,7 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
                                  KP, st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Zbuf, KP, st));
         PROF("permute", st, launch_permute_b(K0P, KP, P.Zbuf, P.Zperm, st));
+        if (panel) PROF("pack_lowp", st, launch_pack_b_lowp(panel, K0P, KP, P.Zbuf, P.Zlp, st));
         // A1_top = A_top - (P - V_top) Z ;  S = P^T A1_top
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Zbuf, KP, 0, 1.0, A, lda, P.A1top,
                                  KP, st));
@@ -120,8 +129,10 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
         Ls[0].Z = P.Zperm;
         Ls[0].Nc = P.Nc;
         Ls[0].Nglob = P.Nperm;
+        Ls[0].Zlp = P.Zlp;
+        Ls[0].Nlp = P.Nlp;
     }
-    rc = tsqr_factor(P.ts, Ls, K0P, R, ldr, st);
+    rc = tsqr_factor(P.ts, Ls, K0P, R, ldr, st, panel);
     if (rc) return rc;
 
     if (k0 > 0) {
@@ -133,19 +144,20 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
                                  P.Nglob, KP, st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 0, P.Nglob, KP, st));
         PROF("permute", st, launch_permute_b(K0P, KP, P.Nglob, P.Nperm, st));
+        if (panel) PROF("pack_lowp", st, launch_pack_b_lowp(panel, K0P, KP, P.Nglob, P.Nlp, st));
         // Q_top = -(P - V_top) N
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Nglob, KP, 0, 0.0, nullptr, 0, Q, ldq,
                                  st));
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Nglob, KP, 0, 1.0, Q, ldq, Q, ldq,
                                  st));
     }
-    return tsqr_form0(P.ts, Ls, K0P, st);
+    return tsqr_form0(P.ts, Ls, K0P, st, panel);
 }
 
-size_t two_stage_bytes(int64_t n, int64_t k0, int64_t k) {
+size_t two_stage_bytes(int64_t n, int64_t k0, int64_t k, int panel = 0) {
     if (k == 0) return 0;
     TwoStagePlan P;
-    make_plan(n, k0, k, nullptr, P);
+    make_plan(n, k0, k, nullptr, P, panel);
     return P.bytes;
 }
 
@@ -199,11 +211,9 @@ int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, con
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
     if (!bytes) return set_err(-6, "bytes must not be NULL");
-    (void)opts;
-    if (k == 0) { *bytes = 0; return 0; }
-    TwoStagePlan P;
-    make_plan(n, k0, k, nullptr, P);
-    *bytes = P.bytes;
+    const int panel = opts ? opts->panel : 0;
+    if (panel < THO_PANEL_F64 || panel > THO_PANEL_BF16) return set_err(-5, "unknown panel precision");
+    *bytes = two_stage_bytes(n, k0, k, panel);
     return 0;
 }
 
@@ -213,17 +223,17 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
     if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented");
-    if (opts && (opts->p_choice != THO_P_QR || opts->panel != THO_PANEL_F64 || opts->flags != 0))
-        return set_err(THO_E_UNSUPPORTED, "only p_choice=THO_P_QR, panel=THO_PANEL_F64 are implemented");
+    const int panel = opts ? opts->panel : 0;
+    if (opts && (opts->p_choice != THO_P_QR || opts->flags != 0))
+        return set_err(THO_E_UNSUPPORTED, "only p_choice=THO_P_QR without flags is implemented");
+    if (panel < THO_PANEL_F64 || panel > THO_PANEL_BF16) return set_err(-15, "unknown panel precision");
     if (k == 0) return 0;
     rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds);
     if (rc) return rc;
     if (!ws) return set_err(-16, "workspace is NULL");
-    TwoStagePlan P;
-    make_plan(n, k0, k, nullptr, P);
-    if (ws_bytes < P.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");
+    if (ws_bytes < two_stage_bytes(n, k0, k, panel)) return set_err(THO_E_WORKSPACE, "workspace too small");
     return run_two_stage(n, k0, k, (const double*)V_, ldv, (const double*)A_, lda, (double*)Q_, ldq, (double*)R_, ldr,
-                         (double*)S_, lds, ws, (hipStream_t)stream);
+                         (double*)S_, lds, ws, (hipStream_t)stream, panel);
 }
 
 int tho_hhqr_full_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts, size_t* bytes) {

@@ -185,18 +185,20 @@ std::vector<TsqrLevel> tsqr_levels(const TsqrPlan& T, const double* X, int64_t l
     return Ls;
 }
 
-int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* R, int64_t ldr, hipStream_t st) {
+int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* R, int64_t ldr, hipStream_t st,
+                int panel) {
     const int nl = (int)Ls.size();
     for (int l = 0; l < nl; l++)
-        PROF(l == 0 ? "leaf_l0" : "leaf_up", st, launch_tsqr_leaf(T.KP, l == 0 ? k0p : 0, Ls[l], st));
+        PROF(l == 0 ? "leaf_l0" : "leaf_up", st,
+             launch_tsqr_leaf(T.KP, l == 0 ? k0p : 0, l == 0 ? panel : 0, Ls[l], st));
     // R with nonnegative diagonal; the top-level Q starts from the sign matrix
     PROF("finish_r", st, launch_finish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
-    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(T.KP, 0, Ls[l], st));
+    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(T.KP, 0, 0, Ls[l], st));
     return 0;
 }
 
-int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st) {
-    PROF("form_l0", st, launch_tsqr_form(T.KP, k0p, Ls[0], st));
+int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel) {
+    PROF("form_l0", st, launch_tsqr_form(T.KP, k0p, panel, Ls[0], st));
     return 0;
 }
 
@@ -210,11 +212,15 @@ XtyPlan xty_plan(int64_t nrows) {
 }
 
 int xty(const XtyPlan& xp, int64_t nrows, const double* X, int64_t ldx, int p, const double* Y, int64_t ldy, int q,
-        double* part, double* out, hipStream_t st, const char* name) {
+        double* part, double* out, hipStream_t st, const char* name, int panel) {
     const int pp = k0p_of(p), qp = kp_of(q);
     if (pp == 0) return 0;
-    PROF(name, st, launch_xty_partial(pp / 16, qp / 16, nrows, X, ldx, p, Y, ldy, q, xp.nblk, xp.rows_per_blk, part,
-                                      st));
+    if (panel != 0)
+        PROF(name, st, launch_xty_lowp(panel, pp / 16, qp / 16, nrows, X, ldx, p, Y, ldy, q, xp.nblk, xp.rows_per_blk,
+                                       part, st));
+    else
+        PROF(name, st, launch_xty_partial(pp / 16, qp / 16, nrows, X, ldx, p, Y, ldy, q, xp.nblk, xp.rows_per_blk,
+                                          part, st));
     PROF("reduce_parts", st, launch_reduce_parts(xp.nblk, (int64_t)pp * qp, part, out, st));
     return 0;
 }

@@ -106,10 +106,11 @@ std::vector<TsqrLevel> tsqr_levels(const TsqrPlan& T, const double* X, int64_t l
 
 // Leaf levels, R with nonnegative diagonal into R (ld ldr), and the
 // formation of every level above 0.  k0p is the V width fused into level 0
-// (0: none).
-int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* R, int64_t ldr, hipStream_t st);
+// (0: none); panel selects the arithmetic of level 0's V products.
+int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* R, int64_t ldr, hipStream_t st,
+                int panel = 0);
 // Formation of level 0 (rows of Q into Ls[0].Y).
-int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st);
+int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel = 0);
 
 // Split-n reduction out = X^T Y over nrows rows (X: p <= 128 columns, Y:
 // q <= 64 columns); `out` is k0p_of(p) x kp_of(q), ld kp_of(q); `part` holds
@@ -119,7 +120,8 @@ struct XtyPlan {
     int64_t rows_per_blk;
 };
 XtyPlan xty_plan(int64_t nrows);
+// panel != 0: reduced-precision products (launch_xty_lowp).
 int xty(const XtyPlan& xp, int64_t nrows, const double* X, int64_t ldx, int p, const double* Y, int64_t ldy, int q,
-        double* part, double* out, hipStream_t st, const char* name);
+        double* part, double* out, hipStream_t st, const char* name, int panel = 0);
 
 }  // namespace tho

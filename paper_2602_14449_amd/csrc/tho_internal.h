@@ -34,6 +34,9 @@ struct TsqrLevel {
     const double* Z;  // K0P x KP Z of the update of A, in B-operand order (k_permute_b)
     double* Nc;       // per chunk KP x K0P: Q_chunk^T V_chunk (leaf output)
     const double* Nglob;  // K0P x KP N = T^{-1} G, in B-operand order (form input)
+    // reduced-precision panels: Z and N packed by launch_pack_b_lowp
+    const void* Zlp;
+    const void* Nlp;
     // per-tile storage
     double* tau;      // [nchunk * maxtiles][KP]
     double* Tt;       // [nchunk * maxtiles][KP * KP]
@@ -101,8 +104,18 @@ hipError_t launch_rows_gemm(const RowsGemm& g, hipStream_t st);
 hipError_t launch_pack_b(int p, int q, const double* src, int64_t lds, int trans, double scale, int kpad, int qp,
                          double* dst, hipStream_t st);
 
-// kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term)
-hipError_t launch_tsqr_leaf(int kp, int k0p, const TsqrLevel& L, hipStream_t st);
-hipError_t launch_tsqr_form(int kp, int k0p, const TsqrLevel& L, hipStream_t st);
+// kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term); panel
+// 0 = FP64, 1 = FP32 hi + lo, 2 = BF16 for the V products (k0p > 0 only).
+hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
+hipError_t launch_tsqr_form(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
+
+// Reduced-precision panels (k_lowp.hip): C = X^T Y with FP32 hi + lo or
+// BF16 products (same layout as launch_xty_partial), and the packing of a
+// dense K0P x KP FP64 matrix into the B-operand order of the fused kernels.
+hipError_t launch_xty_lowp(int panel, int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
+                           const double* Y, int64_t ldy, int q, int nblk, int64_t rows_per_blk, double* part,
+                           hipStream_t st);
+size_t lowp_pack_bytes(int panel, int K0P, int KP);
+hipError_t launch_pack_b_lowp(int panel, int K0P, int KP, const double* src, void* dst, hipStream_t st);
 
 }  // namespace tho
