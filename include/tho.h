@@ -161,6 +161,49 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                            void* dV, int64_t lddv, void* dA, int64_t ldda,
                            const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Batched problems (many independent (V, A) pairs of uneven sizes).
+ * Each problem runs Algorithm 1 (second choice of P) exactly as
+ * tho_two_stage computes it, except that its Householder QR is one chunk of
+ * tiles (no reduction tree): the whole problem is processed by one
+ * workgroup of a single persistent kernel, which takes problems longest
+ * first from a device work counter.  Plan creation validates the problems,
+ * lays out each problem's part of the caller's workspace, autotunes the tile
+ * height (128 or 256 rows) and the number of persistent workgroups by timing
+ * them on the batch itself (cached per batch signature for the life of the
+ * process), and captures the launches into a HIP graph.  The plan binds the
+ * problem pointers and the workspace: tho_batched_run replays the graph on
+ * `stream` and may be called any number of times while the buffers live.
+ * Plan creation allocates small device descriptor arrays (freed by
+ * tho_plan_destroy), synchronizes with `stream` once, and runs the batch a
+ * few times while tuning (outputs are overwritten).  Real FP64 only,
+ * default options only. */
+#define THO_BATCHED_MAX_K0 64
+
+typedef struct {
+    int64_t n, k0, k;      /* n >= k0 + k, 0 <= k0 <= 64, 0 <= k <= 64 */
+    const void* V; int64_t ldv;
+    const void* A; int64_t lda;
+    void* Q; int64_t ldq;
+    void* R; int64_t ldr;
+    void* S; int64_t lds;
+} tho_problem_t;
+
+typedef struct tho_plan_s* tho_plan_t;
+
+/* Workspace bytes for a batch (arguments: 1 count, 2 problems (host array),
+ * 3 opts, 4 bytes out).  An invalid problem returns -2 and names it in
+ * tho_last_error(). */
+int tho_batched_workspace(int32_t count, const tho_problem_t* problems, const tho_opts_t* opts, size_t* bytes);
+/* Arguments: 1 count, 2 problems (host array, copied), 3 ws, 4 ws_bytes,
+ * 5 opts, 6 stream, 7 plan out. */
+int tho_batched_plan_create(int32_t count, const tho_problem_t* problems, void* ws, size_t ws_bytes,
+                            const tho_opts_t* opts, void* stream, tho_plan_t* plan);
+int tho_batched_run(tho_plan_t plan, void* stream);
+/* Autotuner result: tile height in rows, persistent workgroups, and the best
+ * measured batch time in ms (0 when the choice came from the cache). */
+int tho_batched_plan_info(tho_plan_t plan, int32_t* tile_rows, int32_t* grid, double* tuned_ms);
+int tho_plan_destroy(tho_plan_t plan);
+
 /* Benchmark instrumentation (not needed for normal use).
  * tho_profile_enable(1) makes every later call record a pair of hipEvents on
  * its stream around each kernel it launches.  tho_profile_collect() waits

@@ -66,11 +66,32 @@ tho_two_stage_backward = _proto(
      c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
      ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
 
+class Problem(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("k0", c_i64), ("k", c_i64),
+                ("V", c_vp), ("ldv", c_i64), ("A", c_vp), ("lda", c_i64),
+                ("Q", c_vp), ("ldq", c_i64), ("R", c_vp), ("ldr", c_i64),
+                ("S", c_vp), ("lds", c_i64)]
+
+
+tho_batched_workspace = _proto(
+    "tho_batched_workspace", ctypes.c_int,
+    [c_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_batched_plan_create = _proto(
+    "tho_batched_plan_create", ctypes.c_int,
+    [c_i32, ctypes.POINTER(Problem), c_vp, c_sz, ctypes.POINTER(Opts), c_vp, ctypes.POINTER(c_vp)])
+tho_batched_run = _proto("tho_batched_run", ctypes.c_int, [c_vp, c_vp])
+tho_batched_plan_info = _proto(
+    "tho_batched_plan_info", ctypes.c_int,
+    [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_double)])
+tho_plan_destroy = _proto("tho_plan_destroy", ctypes.c_int, [c_vp])
+
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
             "tho_two_stage_workspace", "tho_two_stage",
             "tho_hhqr_full_workspace", "tho_hhqr_full",
             "tho_bcgs_workspace", "tho_bcgs",
-            "tho_two_stage_backward_workspace", "tho_two_stage_backward"]
+            "tho_two_stage_backward_workspace", "tho_two_stage_backward",
+            "tho_batched_workspace", "tho_batched_plan_create", "tho_batched_run",
+            "tho_batched_plan_info", "tho_plan_destroy"]
 
 THO_F64 = 0
 THO_C128 = 1

@@ -169,6 +169,80 @@ def two_stage_backward(V, A, Q, R, gQ, gR, gS=None, *, workspace=None):
     return dV, dA
 
 
+class BatchedPlan:
+    """Many independent two-stage problems (V_i, A_i) in one persistent,
+    graph-captured launch.  Allocates the outputs and the workspace, binds
+    them into a plan (autotuned at creation) and replays it with run()."""
+
+    def __init__(self, pairs):
+        if len(pairs) == 0:
+            raise ValueError("empty batch")
+        dev = pairs[0][1].device
+        self.pairs = pairs
+        self.outputs = []
+        probs = (L.Problem * len(pairs))()
+        for i, (V, A) in enumerate(pairs):
+            if V.dtype != torch.float64 or A.dtype != torch.float64:
+                raise TypeError("the batched path is real float64")
+            if not (V.is_cuda and A.is_cuda and A.device == dev and V.device == dev):
+                raise ValueError("all tensors must be on the same GPU")
+            n, k0 = V.shape
+            k = A.shape[1]
+            Q = torch.empty((n, k), dtype=A.dtype, device=dev)
+            R = torch.empty((k, k), dtype=A.dtype, device=dev)
+            S = torch.empty((k0, k), dtype=A.dtype, device=dev)
+            self.outputs.append((Q, R, S))
+            p = probs[i]
+            p.n, p.k0, p.k = n, k0, k
+            p.V, p.ldv = _ptr(V), _ld(V, "V")
+            p.A, p.lda = _ptr(A), _ld(A, "A")
+            p.Q, p.ldq = _ptr(Q), _ld(Q, "Q")
+            p.R, p.ldr = _ptr(R), _ld(R, "R")
+            p.S, p.lds = _ptr(S), (_ld(S, "S") if k0 > 0 else max(k, 1))
+        self._probs = probs
+        o = _opts()
+        nb = L.c_sz(0)
+        L.check(L.tho_batched_workspace(len(pairs), probs, ctypes.byref(o), ctypes.byref(nb)),
+                "tho_batched_workspace")
+        self.workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=dev)
+        self.device = dev
+        h = L.c_vp()
+        L.check(L.tho_batched_plan_create(len(pairs), probs, self.workspace.data_ptr(),
+                                          self.workspace.numel(), ctypes.byref(o), _stream(dev),
+                                          ctypes.byref(h)), "tho_batched_plan_create")
+        self._plan = h
+
+    def run(self):
+        L.check(L.tho_batched_run(self._plan, _stream(self.device)), "tho_batched_run")
+        return self.outputs
+
+    def info(self):
+        tr, gr, ms = L.c_i32(0), L.c_i32(0), ctypes.c_double(0)
+        L.check(L.tho_batched_plan_info(self._plan, ctypes.byref(tr), ctypes.byref(gr), ctypes.byref(ms)),
+                "tho_batched_plan_info")
+        return {"tile_rows": tr.value, "workgroups": gr.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            torch.cuda.synchronize(self.device)
+            L.tho_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def two_stage_batched(pairs):
+    """Two-stage orthogonalization of every (V_i, A_i): list of (Q, R, S)."""
+    plan = BatchedPlan(pairs)
+    out = plan.run()
+    plan.close()
+    return out
+
+
 class TwoStageFunction(torch.autograd.Function):
     """(V, A) -> (Q, R, S) with the hand-written adjoint as its backward.
     Saves only V, A, Q, R; the WY factors are recomputed in the adjoint."""

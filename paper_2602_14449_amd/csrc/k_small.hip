@@ -4,6 +4,7 @@
 // triangular solves with T, small products).
 #include "tho_device.h"
 #include "tho_internal.h"
+#include "small_dev.h"
 
 namespace tho {
 
@@ -168,118 +169,10 @@ __global__ __launch_bounds__(1024) void k_trsm_lower(int n, int m, const double*
     for (int e = tid; e < n * m; e += nt) B[(int64_t)(e / m) * ldb + (e % m)] = Bs[e];
 }
 
-// Householder QR of the square top block V_top (n x n, n <= 128) with
-// nonnegative diag(R) (the second choice of P, §3.2), entirely in LDS, then
-//   P = -Q1  and  T = I + R1^T  (lower triangular; the form of Appendix B.2)
-// written to P (ld n) and T (ld n).  Reflectors use the same convention as
-// the rest of the library (beta = -sign(alpha) * norm, tau = 0 for a zero
-// subcolumn); Q is formed in place from the reflectors (backward
-// accumulation), then columns of Q / rows of R are scaled by sign(R_jj).
 __global__ __launch_bounds__(1024) void k_qr_top(int n, const double* __restrict__ Vt, int64_t ldv,
                                                  double* __restrict__ P, double* __restrict__ T) {
     extern __shared__ double sm[];
-    const int ld = n + 1;
-    double* M = sm;                 // n x ld
-    double* part = M + n * ld;      // 8 x n partial dots
-    double* wv = part + 8 * n;      // n: w_c of the current reflector
-    double* taus = wv + n;          // n
-    double* sgn = taus + n;         // n: sign of R_jj
-    double* red = sgn + n;          // 16 scalars
-    const int tid = threadIdx.x;
-    const int c = tid % 128, rg = tid / 128;  // column, row group (8 groups)
-    for (int e = tid; e < n * n; e += blockDim.x) M[(e / n) * ld + (e % n)] = Vt[(int64_t)(e / n) * ldv + (e % n)];
-    __syncthreads();
-    for (int j = 0; j < n; j++) {
-        // sum of squares of the subcolumn below the pivot
-        double ss = 0.0;
-        if (tid < 64) {
-            for (int i = j + 1 + tid; i < n; i += 64) ss += M[i * ld + j] * M[i * ld + j];
-            ss = sum_wave(ss);
-            if (tid == 0) red[0] = ss;
-        }
-        __syncthreads();
-        const double sig2 = red[0];
-        const double alpha = M[j * ld + j];
-        double beta = alpha, tau = 0.0, scale = 0.0;
-        if (sig2 != 0.0) {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha < 0.0) ? nrm : -nrm;
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        __syncthreads();  // everyone has read M[j][j] and red
-        if (tid > j && tid < n) M[tid * ld + j] *= scale;
-        if (tid == 0) { taus[j] = tau; M[j * ld + j] = beta; }
-        __syncthreads();
-        // w_c = M[j][c] + sum_{i>j} v_i M[i][c] for c > j
-        if (c < n && c > j) {
-            double s = 0.0;
-            for (int i = j + 1 + rg; i < n; i += 8) s += M[i * ld + j] * M[i * ld + c];
-            part[rg * n + c] = s;
-        }
-        __syncthreads();
-        if (tid < n && tid > j) {
-            double s = M[j * ld + tid];
-            for (int r = 0; r < 8; r++) s += part[r * n + tid];
-            wv[tid] = s;
-        }
-        __syncthreads();
-        if (c < n && c > j) {
-            const double tw = tau * wv[c];
-            if (rg == 0) M[j * ld + c] -= tw;
-            for (int i = j + 1 + rg; i < n; i += 8) M[i * ld + c] -= tw * M[i * ld + j];
-        }
-        __syncthreads();
-    }
-    // R1 diagonal signs and T = I + D R1^T (rows of R scaled by d)
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, jj = e % n;  // T[i][jj] = delta + d_jj R[jj][i] for jj <= i
-        double v = (i == jj) ? 1.0 : 0.0;
-        if (jj <= i) {
-            const double d = (M[jj * ld + jj] < 0.0) ? -1.0 : 1.0;
-            v += d * M[jj * ld + i];
-        }
-        T[(int64_t)i * n + jj] = v;
-    }
-    // keep the diagonal signs before Q overwrites M
-    if (tid < n) sgn[tid] = (M[tid * ld + tid] < 0.0) ? -1.0 : 1.0;
-    __syncthreads();
-    // form Q in place (backward accumulation of the reflectors)
-    for (int j = n - 1; j >= 0; j--) {
-        const double tau = taus[j];
-        if (j < n - 1) {
-            if (c < n && c > j) {
-                double s = 0.0;
-                for (int i = j + 1 + rg; i < n; i += 8) s += M[i * ld + j] * M[i * ld + c];
-                part[rg * n + c] = s;
-            }
-            __syncthreads();
-            if (tid < n && tid > j) {
-                // row j of an already formed column c > j is zero
-                double s = M[j * ld + tid];
-                for (int r = 0; r < 8; r++) s += part[r * n + tid];
-                wv[tid] = s;
-            }
-            __syncthreads();
-            if (c < n && c > j) {
-                const double tw = tau * wv[c];
-                if (rg == 0) M[j * ld + c] -= tw;
-                for (int i = j + 1 + rg; i < n; i += 8) M[i * ld + c] -= tw * M[i * ld + j];
-            }
-            __syncthreads();
-        }
-        if (tid < n) {
-            if (tid > j) M[tid * ld + j] = -tau * M[tid * ld + j];
-            else if (tid == j) M[j * ld + j] = 1.0 - tau;
-            else M[tid * ld + j] = 0.0;
-        }
-        __syncthreads();
-    }
-    // P = -Q D
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, jj = e % n;
-        P[(int64_t)i * n + jj] = -M[i * ld + jj] * sgn[jj];
-    }
+    qr_top_body(n, Vt, ldv, P, T, sm);
 }
 
 // Phase-normalize the top-level R (k x k, rows of ld KP in Rin) and write
@@ -428,7 +321,7 @@ hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int tra
 
 hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double* T, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const size_t shm = ((size_t)n * (n + 1) + 8 * n + 3 * n + 16) * sizeof(double);
+    const size_t shm = (size_t)qr_top_lds(n) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void*)k_qr_top, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -1,669 +1,24 @@
-// Chunked tall-skinny Householder QR (the QR of the bottom block in
-// Algorithm 1) and the explicit formation of Q, for gfx950.
-//
-// Structure.  The m x k matrix is split into `nchunk` row chunks, one
-// workgroup each.  A workgroup walks its chunk in tiles of 128 or 256 rows and keeps
-// a running k x k triangle R in LDS (a flat reduction tree inside the chunk):
-//   tile 0:  plain Householder QR of the tile,          X_0 = H_0 [I; 0] R
-//   tile t:  QR of [R; X_t] with structured reflectors   u_j = [e_j; y_j]
-// Every tile stores its Householder vectors Y_t (into the output buffer, in
-// place of the rows of Q they will become) and its compact-WY factor T_t
-// (H_t = I - U_t T_t U_t^T), so Q can be formed later without refactoring.
-// The chunk R factors are stacked into the matrix of the next level, which is
-// reduced the same way until one chunk remains.
-//
-// Level 0 (the bottom n - k0 rows of A) is fused with the generalized
-// Householder step of Algorithm 1: the tile loaded from A is updated to
-// A + V Z on MFMA before factorization (the update of A), and the chunk accumulates
-// N_c = V_chunk^T Q_chunk, which gives W^T [0; Q_] = -sum_c N_c G_c without
-// another pass over V (formation of Q).
-//
-// Register tile: 4 wavefronts x 32 or 64 rows; each wavefront keeps two or
-// four 16 x KP row blocks in FP64 MFMA accumulator layout (tho_device.h), so the
-// column reductions of the Householder loop are shuffles across the four
-// 16-lane groups plus one LDS exchange across wavefronts, and the tile is
-// directly an MFMA operand for products that contract over rows.
-#include "tho_device.h"
-#include "tho_internal.h"
-#include "tho_lowp.h"
+// Kernels and launchers of the chunked tall-skinny Householder QR and of the
+// formation of Q (device code in tsqr_dev.h).
+#include "tsqr_dev.h"
 
 namespace tho {
 
-#ifdef THO_PHASE_TIMING
-__device__ long long g_phase_ts[4096];
-#define PHASE_TS(t, ph) \
-    do { if (blockIdx.x == 0 && threadIdx.x == 0 && (t) < 64) g_phase_ts[(t) * 8 + (ph)] = clock64(); } while (0)
-#else
-#define PHASE_TS(t, ph) do {} while (0)
-#endif
-
-namespace {
-
-constexpr int NW = LEAF_WAVES;     // wavefronts per workgroup
-
-// Tile geometry per column count: the register tile is RB 16-row blocks per
-// wavefront (KP = 64: 2 blocks, so that a wavefront fits in 256 registers
-// and two workgroups share a compute unit; narrower: 4 blocks).
-template <int KP>
-struct Geo {
-    static constexpr int RB = (KP >= 64) ? 2 : 4;  // 16-row blocks per wavefront
-    static constexpr int RPW = 16 * RB;            // rows per wavefront
-    static constexpr int TB = NW * RPW;            // rows per tile
-};
-
-// Lane id the compiler cannot treat as loop invariant: per-lane address
-// offsets derived from it are recomputed in each phase instead of being
-// hoisted and kept live across the Householder loop (register pressure).
-__device__ __forceinline__ int opaque_lane() {
-    int x = threadIdx.x & 63;
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
-template <int RPW>
-__device__ __forceinline__ int tile_row(int w, int rb, int l, int v) {
-    return RPW * w + 16 * rb + drow(l, v);
-}
-
-template <int KP, int K0P>
-struct LeafLds {
-    static constexpr int LDT = KP + 1;
-    static constexpr int total = 2 * KP * LDT + Geo<KP>::TB + 2 * KP + 2 * NW * KP + KP;
-};
-
-template <int KP, int K0P>
-struct FormLds {
-    static constexpr int LDT = KP + 1;
-    static constexpr int total = KP * LDT + KP * LDT;
-};
-
-// Householder QR of the register tile x (PLAIN: the tile alone; otherwise
-// [slot; tile] with the running triangle in `slot`).  One cross-wavefront
-// exchange per column: every wavefront reduces, over its "sub" rows (below
-// the pivot), the dot products d_c of the unscaled pivot column with every
-// column c.  With the pivot-row values p_c and the reflector
-// u = [1; x_sub / (alpha - beta)]:
-//   sigma^2 = d_j,   w_c = u^T x_c = p_c + d_c / (alpha - beta),
-// and for c < j, w_c = u_c^T u_j feeds the T recurrence (Gm).
-// Returns beta of the last column; for a structured tile the caller stores it
-// into slot(k-1, k-1) after the next workgroup barrier (other wavefronts read
-// that entry as the pivot of the last column until then).
-template <int KP, bool PLAIN>
-__device__ __forceinline__ double householder_tile(d4 (&x)[Geo<KP>::RB][KP / 16], int k, int w, double* xcol,
-                                                 double* prow, double* part, double* slot, double* Gm,
-                                                 double* taus) {
-    constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW;
-    constexpr int CT = KP / 16;
-    constexpr int LDT = KP + 1;
-    const int l = opaque_lane(), g = l >> 4, cl = l & 15;
-    double tau_prev = 0.0, beta_prev = 0.0, wl_prev = 0.0;
-    double* xw = xcol + RPW * w;  // this wavefront's pivot column, lane-group order
-    for (int j = 0; j < k; j++) {
-        const int pb = j & 1, ctj = j >> 4, clj = j & 15;
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            if (ct == ctj && cl == clj) {
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) xw[rb * 16 + g * 4 + v] = x[rb][ct][v];
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double xs[RB][4];  // pivot-column value on my sub rows, 0 elsewhere
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const double xv = xw[rb * 16 + g * 4 + v];
-                xs[rb][v] = (!PLAIN || tile_row<RPW>(w, rb, l, v) > j) ? xv : 0.0;
-            }
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            double s = 0.0;
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) s += xs[rb][v] * x[rb][ct][v];
-            s = sum_groups(s);
-            if (g == 0) part[(pb * NW + w) * KP + 16 * ct + cl] = s;
-        }
-        if (PLAIN && w == j / RPW) {
-            // publish the pivot row (row j of the tile)
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int v = 0; v < 4; v++)
-                    if (tile_row<RPW>(w, rb, l, v) == j) {
-#pragma unroll
-                        for (int ct = 0; ct < CT; ct++) prow[pb * KP + 16 * ct + cl] = x[rb][ct][v];
-                    }
-        }
-        __syncthreads();
-
-        // deferred update of slot row j-1 (all its readers are past the barrier)
-        if (!PLAIN && j > 0 && w == 0) {
-            if (l > j - 1 && l < k) slot[(j - 1) * LDT + l] -= tau_prev * wl_prev;
-            if (l == j - 1) slot[(j - 1) * LDT + (j - 1)] = beta_prev;
-        }
-        double dl = 0.0, pl = 0.0;
-        if (l < KP) {
-#pragma unroll
-            for (int ww = 0; ww < NW; ww++) dl += part[(pb * NW + ww) * KP + l];
-            pl = PLAIN ? prow[pb * KP + l] : slot[j * LDT + l];
-        }
-        const double sig2 = __shfl(dl, j);
-        const double alpha = __shfl(pl, j);
-        double beta = alpha, tau = 0.0, scale = 0.0;
-        if (sig2 != 0.0) {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha < 0.0) ? nrm : -nrm;
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        const double wl = pl + scale * dl;
-        if (w == 0) {
-            if (l < j) Gm[j * LDT + l] = wl;
-            if (l == 0) taus[j] = tau;
-        }
-        double wv[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) wv[ct] = __shfl(wl, 16 * ct + cl);
-        double u[RB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int v = 0; v < 4; v++)
-                u[rb][v] = (PLAIN && tile_row<RPW>(w, rb, l, v) == j) ? 1.0 : xs[rb][v] * scale;
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            const int col = 16 * ct + cl;
-            const double coef = (col > j && col < k) ? tau * wv[ct] : 0.0;
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) x[rb][ct][v] -= coef * u[rb][v];
-        }
-        // column j becomes the Householder vector (and beta on the pivot)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            if (ct == ctj && cl == clj) {
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        if (PLAIN) {
-                            const int row = tile_row<RPW>(w, rb, l, v);
-                            if (row > j) x[rb][ct][v] = u[rb][v];
-                            else if (row == j) x[rb][ct][v] = beta;
-                        } else {
-                            x[rb][ct][v] *= scale;
-                        }
-                    }
-            }
-        }
-        tau_prev = tau;
-        beta_prev = beta;
-        wl_prev = wl;
-    }
-    return beta_prev;
-}
-
-}  // namespace
-
 template <int KP, int K0P, int PANEL>
 __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
-    constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
-    constexpr int CT = KP / 16;
-    constexpr int LDT = KP + 1;
-    constexpr bool HASV = K0P > 0;
-    constexpr int KS0 = (K0P > 0) ? K0P / 4 : 1;
-    constexpr int MT0 = (K0P > 0) ? K0P / 16 : 1;  // 16-column blocks of N^T
-    constexpr int NJW = (MT0 + NW - 1) / NW;        // ... owned per wavefront
-
-    extern __shared__ double sm[];
-    double* TG = sm;                    // KP x LDT: T (upper) and Gm (strict lower)
-    double* slot = TG + KP * LDT;       // KP x LDT: running R of the chunk
-    double* xcol = slot + KP * LDT;     // TB: pivot column, RPW rows per wavefront
-    double* prow = xcol + TB;           // 2 x KP: pivot row of the plain tile
-    double* part = prow + 2 * KP;       // 2 x NW x KP: partial dot products
-    double* taus = part + 2 * NW * KP;  // KP: tau of each reflector
-
-    const int tid = threadIdx.x, w = tid >> 6;
-    const int c = blockIdx.x;
-    const int k = L.k;
-    const int k0 = HASV ? L.k0 : 0;
-    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
-    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
-    const int ntiles = (int)((cr1 - cr0 + TB - 1) / TB);
-
-    // The running N_c^T (KP x K0P, = Q_chunk^T V_chunk) lives in L.Nc[c];
-    // wavefront w owns its 16-column blocks nj = w, w + NW, ... (all rows) and
-    // is the only one to read or write them.
-    double* NT = (HASV && k0 > 0) ? L.Nc + (int64_t)c * KP * K0P : nullptr;
-
-    for (int t = 0; t < ntiles; t++) {
-        if (t > 0) __syncthreads();  // readers of TG from the last tile are done
-        const int64_t r0 = cr0 + (int64_t)t * TB;
-        const int trows = (int)((cr1 - r0 < TB) ? (cr1 - r0) : TB);
-        const bool plain = (t == 0);
-        PHASE_TS(t, 0);
-        // uniform (scalar) bases of this tile; per-lane offsets stay 32-bit
-        const double* __restrict__ Xt = L.X + r0 * L.ldx;
-        double* __restrict__ Yt = L.Y + r0 * L.ldy;
-        const double* __restrict__ Vt = HASV ? L.V + r0 * L.ldv : nullptr;
-        const int ldx = (int)L.ldx, ldy = (int)L.ldy, ldv = (int)L.ldv;
-
-        // ---- load the tile (rows r0.., in accumulator layout)
-        d4 x[RB][CT];
-        {
-            const int l = opaque_lane(), cl = l & 15;
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
-                        x[rb][ct][v] = (row < trows && col < k) ? Xt[row * ldx + col] : 0.0;
-                    }
-        }
-
-        // ---- the update of A (Algorithm 1) on these rows: A <- A + V Z  (MFMA; Z is
-        // read in B-operand order from L.Z, see k_permute_b)
-        if (PANEL != PANEL_F64 && HASV && k0 > 0) {
-            vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(x, Vt, ldv, RPW * w, trows, k0, L.Zlp, opaque_lane());
-        } else if (HASV && k0 > 0) {
-            const int l = opaque_lane(), g = l >> 4, cl = l & 15;
-            constexpr int SC = 4;  // K-steps per chunk
-#pragma unroll 2
-            for (int s0 = 0; s0 < KS0; s0 += SC) {
-                double a[RB][SC], b[SC][CT];
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) {
-                    const int vr = RPW * w + 16 * rb + cl;  // A-operand row of this lane
-                    const double* vp = Vt + vr * ldv + g * KS0 + s0;
-#pragma unroll
-                    for (int s = 0; s < SC; s++)
-                        a[rb][s] = (vr < trows && g * KS0 + s0 + s < k0) ? vp[s] : 0.0;
-                }
-#pragma unroll
-                for (int s = 0; s < SC; s++)
-#pragma unroll
-                    for (int ct = 0; ct < CT; ct++) b[s][ct] = L.Z[((s0 + s) * CT + ct) * 64 + l];
-#pragma unroll
-                for (int s = 0; s < SC; s++)
-#pragma unroll
-                    for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                        for (int ct = 0; ct < CT; ct++) x[rb][ct] = mfma(a[rb][s], b[s][ct], x[rb][ct]);
-            }
-        }
-
-        PHASE_TS(t, 1);
-        // ---- Householder QR of the tile (plain) or of [R; tile] (structured)
-        double beta_last;
-        if (plain) beta_last = householder_tile<KP, true>(x, k, w, xcol, prow, part, slot, TG, taus);
-        else beta_last = householder_tile<KP, false>(x, k, w, xcol, prow, part, slot, TG, taus);
-        __syncthreads();
-        // row k-1 of the slot has no trailing columns; only its diagonal changes
-        if (!plain && w == 0 && k > 0 && (threadIdx.x & 63) == k - 1) slot[(k - 1) * LDT + (k - 1)] = beta_last;
-        PHASE_TS(t, 2);
-        // compact-WY factor (H_0 ... H_{k-1} = I - U T U^T):
-        //   T(i,i) = tau_i,  T(i,j) = -tau_j sum_{i<=p<j} T(i,p) u_p^T u_j
-        // Rows of T are independent; four lanes of one wavefront own a row and
-        // sweep its columns (no workgroup barrier).  Gm(j,p) = u_p^T u_j sits
-        // in the strict lower triangle of TG, T in the upper one.
-        {
-            const int ti = tid >> 2, tq = tid & 3;
-            if (ti < k) {
-                if (tq == 0) TG[ti * LDT + ti] = taus[ti];
-                for (int j = ti + 1; j < k; j++) {
-                    double s = 0.0;
-                    for (int p = ti + tq; p < j; p += 4) s += TG[ti * LDT + p] * TG[j * LDT + p];
-                    s += __shfl_xor(s, 1);
-                    s += __shfl_xor(s, 2);
-                    if (tq == 0) TG[ti * LDT + j] = -taus[j] * s;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-            }
-        }
-
-        {
-            const int l = opaque_lane(), cl = l & 15;
-            if (plain) {
-                // R -> slot; registers -> unit lower trapezoidal Y
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
-                            if (row < KP && col < KP) {
-                                const double xv = x[rb][ct][v];
-                                slot[row * LDT + col] = (col >= row && row < k && col < k) ? xv : 0.0;
-                                if (col > row) x[rb][ct][v] = 0.0;
-                                else if (col == row) x[rb][ct][v] = (row < k) ? 1.0 : 0.0;
-                            }
-                        }
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
-                        if (row < trows && col < k) Yt[row * ldy + col] = x[rb][ct][v];
-                    }
-        }
-        __syncthreads();  // T complete, Y rows visible to the whole workgroup
-        {
-            const int64_t ti = (int64_t)c * L.maxtiles + t;
-            double* Tg = L.Tt + ti * KP * KP;
-            for (int e = tid; e < KP * KP; e += blockDim.x) {
-                const int i = e / KP, jj = e % KP;
-                Tg[e] = (jj >= i && jj < k) ? TG[i * LDT + jj] : 0.0;
-            }
-        }
-        PHASE_TS(t, 3);
-
-        // ---- level 0: N_c^T <- Q^T V of the chunk so far, through
-        //   structured tile:  N^T <- N^T - T^T (N^T + Y^T V)
-        //   plain tile 0:     N^T  = V_0[0:k] - L_0 T^T (Y^T V),  L_0 = Y_0[0:k, 0:k]
-        if (HASV && k0 > 0) {
-            const int l = opaque_lane(), g = l >> 4, cl = l & 15;
-            d4 sacc[CT][NJW];
-#pragma unroll
-            for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                for (int q = 0; q < NJW; q++) sacc[mi][q] = d4zero();
-            // B^T = Y^T V over the tile rows (4 rows per K-step)
-            constexpr int US = 2;
-            for (int s0 = 0; s0 < TB / 4; s0 += US) {
-                double ya[US][CT], vb[US][NJW];
-#pragma unroll
-                for (int u = 0; u < US; u++) {
-                    const int row = 4 * (s0 + u) + g;
-                    const bool ok = row < trows;
-#pragma unroll
-                    for (int mi = 0; mi < CT; mi++) {
-                        const int yc = 16 * mi + cl;
-                        ya[u][mi] = (ok && yc < k) ? Yt[row * ldy + yc] : 0.0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < NJW; q++) {
-                        const int vc = 16 * (w + NW * q) + cl;
-                        vb[u][q] = (ok && vc < k0) ? Vt[row * ldv + vc] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < US; u++)
-#pragma unroll
-                    for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                        for (int q = 0; q < NJW; q++) sacc[mi][q] = mfma(ya[u][mi], vb[u][q], sacc[mi][q]);
-            }
-            if (!plain) {
-#pragma unroll
-                for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                    for (int q = 0; q < NJW; q++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
-                            if (cc < K0P) sacc[mi][q][v] += NT[r * K0P + cc];
-                        }
-            }
-            // D^T = T^T S^T, contracting over the rows of S^T (K-step (rb, v)
-            // takes rows 16 rb + l/16 + 4 v, i.e. register v of block rb)
-            d4 dacc[CT][NJW];
-#pragma unroll
-            for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                for (int q = 0; q < NJW; q++) dacc[mi][q] = d4zero();
-#pragma unroll
-            for (int rb = 0; rb < CT; rb++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int p = 16 * rb + drow(l, v);
-#pragma unroll
-                    for (int mi = 0; mi < CT; mi++) {
-                        const int m = 16 * mi + cl;
-                        const double a = (p <= m && m < k) ? TG[p * LDT + m] : 0.0;  // T^T(m, p)
-#pragma unroll
-                        for (int q = 0; q < NJW; q++) dacc[mi][q] = mfma(a, sacc[rb][q][v], dacc[mi][q]);
-                    }
-                }
-            if (!plain) {
-#pragma unroll
-                for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                    for (int q = 0; q < NJW; q++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
-                            if (cc < K0P) NT[r * K0P + cc] -= dacc[mi][q][v];
-                        }
-            } else {
-                // E^T = L_0 D^T, N^T = V_0[0:k] - E^T
-                d4 eacc[CT][NJW];
-#pragma unroll
-                for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                    for (int q = 0; q < NJW; q++) eacc[mi][q] = d4zero();
-#pragma unroll
-                for (int rb = 0; rb < CT; rb++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int p = 16 * rb + drow(l, v);
-#pragma unroll
-                        for (int mi = 0; mi < CT; mi++) {
-                            const int m = 16 * mi + cl;
-                            const double a = (m < k && p < k) ? Yt[m * ldy + p] : 0.0;  // L_0(m, p)
-#pragma unroll
-                            for (int q = 0; q < NJW; q++) eacc[mi][q] = mfma(a, dacc[rb][q][v], eacc[mi][q]);
-                        }
-                    }
-#pragma unroll
-                for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                    for (int q = 0; q < NJW; q++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
-                            const double vt = (r < k && cc < k0) ? Vt[r * ldv + cc] : 0.0;
-                            if (cc < K0P) NT[r * K0P + cc] = vt - eacc[mi][q][v];
-                        }
-            }
-        }
-    }
-    PHASE_TS(63, 0);
-
-    // ---- chunk output: R_c into the next level
-    for (int e = tid; e < k * KP; e += blockDim.x) {
-        const int i = e / KP, jj = e % KP;
-        L.Rnext[((int64_t)c * k + i) * L.ldrn + jj] = (jj < k && jj >= i) ? slot[i * LDT + jj] : 0.0;
-    }
+    leaf_chunk<KP, K0P, PANEL, 0>(L, blockIdx.x);
 }
 
-// Form the explicit Q of one level from the stored Householder vectors:
-// chunk c's rows of Q are Q_chunk G_c, with G_c read from the formed level
-// above (or the phase signs at the top).  Tiles are visited last to first;
-// C carries G_c down the flat tree:
-//   structured tile t:  K = T_t C,                rows = -Y_t K,  C <- C - K
-//   plain tile 0:       K = T_0 (Y_0[0:k]^T C),   rows = [C; 0] - Y_0 K
-// Level 0 adds V N (formation of Q in Algorithm 1: Q_low = Q_ + V_low N).
-// Output rows overwrite the Householder vectors in place.
 template <int KP, int K0P, int PANEL>
 __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
-    constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
-    constexpr int CT = KP / 16;
-    constexpr int LDT = KP + 1;
-    constexpr bool HASV = K0P > 0;
-    constexpr int KS0 = (K0P > 0) ? K0P / 4 : 1;
-    constexpr int KSK = KP / 4;
-    constexpr int NTK = CT * CT;
-    constexpr int NTKW = (NTK + NW - 1) / NW;
-
-    extern __shared__ double sm[];
-    double* Cm = sm;              // KP x LDT
-    double* Kp = Cm + KP * LDT;   // KP x LDT region: E (plain) then -K permuted
-    const double* Np = L.Nglob;   // N in B-operand order (see k_permute_b)
-
-    const int tid = threadIdx.x, w = tid >> 6;
-    const int c = blockIdx.x;
-    const int k = L.k;
-    const int k0 = HASV ? L.k0 : 0;
-    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
-    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
-    const int ntiles = (int)((cr1 - cr0 + TB - 1) / TB);
-
-    {
-        const double* G = L.Gin + (int64_t)c * L.gstride * L.ldg;
-        for (int e = tid; e < KP * KP; e += blockDim.x) {
-            const int i = e / KP, jj = e % KP;
-            Cm[i * LDT + jj] = (i < k && jj < k) ? G[(int64_t)i * L.ldg + jj] : 0.0;
-        }
-    }
-    __syncthreads();
-
-    for (int t = ntiles - 1; t >= 0; t--) {
-        const int64_t r0 = cr0 + (int64_t)t * TB;
-        const int trows = (int)((cr1 - r0 < TB) ? (cr1 - r0) : TB);
-        const bool plain = (t == 0);
-        const double* Tg = L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP;
-        double* __restrict__ Yt = L.Y + r0 * L.ldy;
-        const double* __restrict__ Vt = HASV ? L.V + r0 * L.ldv : nullptr;
-        const int ldy = (int)L.ldy, ldv = (int)L.ldv;
-        const int l = opaque_lane(), g = l >> 4, cl = l & 15;
-
-        const double* src = Cm;
-        if (plain) {
-            d4 e[NTKW];
-#pragma unroll
-            for (int i = 0; i < NTKW; i++) e[i] = d4zero();
-#pragma unroll
-            for (int s = 0; s < KSK; s++)
-#pragma unroll
-                for (int i = 0; i < NTKW; i++) {
-                    const int id = w + NW * i;
-                    if (id < NTK) {
-                        const int mi = id / CT, nj = id % CT;
-                        const int yr = 4 * s + g, yc = 16 * mi + cl;
-                        const double a = (yr < k && yc < k) ? Yt[yr * ldy + yc] : 0.0;
-                        e[i] = mfma(a, Cm[(4 * s + g) * LDT + 16 * nj + cl], e[i]);
-                    }
-                }
-#pragma unroll
-            for (int i = 0; i < NTKW; i++) {
-                const int id = w + NW * i;
-                if (id < NTK) {
-                    const int mi = id / CT, nj = id % CT;
-#pragma unroll
-                    for (int v = 0; v < 4; v++) Kp[(16 * mi + drow(l, v)) * LDT + 16 * nj + cl] = e[i][v];
-                }
-            }
-            __syncthreads();
-            src = Kp;
-        }
-        d4 kk[NTKW];
-#pragma unroll
-        for (int i = 0; i < NTKW; i++) kk[i] = d4zero();
-#pragma unroll
-        for (int s = 0; s < KSK; s++)
-#pragma unroll
-            for (int i = 0; i < NTKW; i++) {
-                const int id = w + NW * i;
-                if (id < NTK) {
-                    const int mi = id / CT, nj = id % CT;
-                    const double a = Tg[(16 * mi + cl) * KP + 4 * s + g];
-                    kk[i] = mfma(a, src[(4 * s + g) * LDT + 16 * nj + cl], kk[i]);
-                }
-            }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NTKW; i++) {
-            const int id = w + NW * i;
-            if (id < NTK) {
-                const int mi = id / CT, nj = id % CT;
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int r = 16 * mi + drow(l, v), cc = 16 * nj + cl;
-                    const int gg = r / KSK, s = r % KSK;
-                    Kp[(s * CT + (cc >> 4)) * 64 + 16 * gg + (cc & 15)] = -kk[i][v];
-                    if (!plain) Cm[r * LDT + cc] -= kk[i][v];
-                }
-            }
-        }
-        __syncthreads();
-
-        d4 acc[RB][CT];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
-                    acc[rb][ct][v] = (plain && row < k && col < k) ? Cm[row * LDT + col] : 0.0;
-                }
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const int yr = RPW * w + 16 * rb + cl;
-            const bool ok = yr < trows;
-            {
-                const double* yp = Yt + yr * ldy + g * KSK;
-                double a[KSK];
-#pragma unroll
-                for (int s = 0; s < KSK; s++) a[s] = (ok && g * KSK + s < k) ? yp[s] : 0.0;
-#pragma unroll
-                for (int s = 0; s < KSK; s++)
-#pragma unroll
-                    for (int ct = 0; ct < CT; ct++)
-                        acc[rb][ct] = mfma(a[s], Kp[(s * CT + ct) * 64 + l], acc[rb][ct]);
-            }
-            if (PANEL == PANEL_F64 && HASV && k0 > 0) {
-                const double* vp = Vt + yr * ldv + g * KS0;
-                constexpr int HS = (KS0 > 16) ? 16 : KS0;
-#pragma unroll
-                for (int s0 = 0; s0 < KS0; s0 += HS) {
-                    double a[HS];
-#pragma unroll
-                    for (int s = 0; s < HS; s++) a[s] = (ok && g * KS0 + s0 + s < k0) ? vp[s0 + s] : 0.0;
-#pragma unroll
-                    for (int s = 0; s < HS; s++)
-#pragma unroll
-                        for (int ct = 0; ct < CT; ct++)
-                            acc[rb][ct] = mfma(a[s], Np[((s0 + s) * CT + ct) * 64 + l], acc[rb][ct]);
-                }
-            }
-        }
-        if (PANEL != PANEL_F64 && HASV && k0 > 0)
-            vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(acc, Vt, ldv, RPW * w, trows, k0, L.Nlp, l);
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
-                    if (row < trows && col < k) Yt[row * ldy + col] = acc[rb][ct][v];
-                }
-        __syncthreads();
-    }
+    form_chunk<KP, K0P, PANEL, 0>(L, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- launchers
 
 template <int KP, int K0P, int PANEL>
 static hipError_t leaf_t(const TsqrLevel& L, hipStream_t st) {
-    const size_t shm = LeafLds<KP, K0P>::total * sizeof(double);
+    const size_t shm = LeafLds<KP>::total * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_leaf<KP, K0P, PANEL>,
@@ -677,7 +32,7 @@ static hipError_t leaf_t(const TsqrLevel& L, hipStream_t st) {
 
 template <int KP, int K0P, int PANEL>
 static hipError_t form_t(const TsqrLevel& L, hipStream_t st) {
-    const size_t shm = FormLds<KP, K0P>::total * sizeof(double);
+    const size_t shm = FormLds<KP>::total * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_form<KP, K0P, PANEL>,

@@ -75,6 +75,28 @@ hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* N
 hipError_t launch_small_ew(int M, int N, double a, const double* X, int64_t ldx, int tx, double b, const double* Y,
                            int64_t ldy, int ty, double c, int mode, double* D, int64_t ldd, hipStream_t st);
 
+// One problem of the batched path (k_batched.hip): inputs/outputs as in
+// tho_two_stage plus its own workspace pieces (all device pointers).
+struct BatchedInst {
+    int64_t n;
+    int k0, k, K0P, pad;
+    const double* V;
+    const double* A;
+    double *Q, *R, *S;
+    int64_t ldv, lda, ldq, ldr, lds;
+    double *Pm, *Tm;        // k0 x k0 (ld k0): P and T
+    double *Zperm, *Nperm;  // K0P x KP in B-operand order
+    double* Nc;             // KP x K0P: N_c^T from the leaf
+    double *Rtop, *G0;      // KP x KP
+};
+int batched_tile_rows(int kp, int rbo);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+// Persistent launch over `count` problems of one (kp, k0p) class in the
+// order `order` (kp in {16, 32, 64}, k0p in {0, 16, 32, 64}, rbo = 16-row
+// blocks per wavefront of a tile: 2 or 4; kp = 64 takes 2 only).
+hipError_t launch_batched(int kp, int k0p, int rbo, const BatchedInst* insts, const TsqrLevel* levels,
+                          const int* order, int count, int* counter, int grid, hipStream_t st);
+
 // Row-streaming panel product Out = X + sum_t Y_t B_t (k_stream.hip).
 // X may be NULL (taken as 0) and may alias Out; q <= 128 output columns;
 // each B_t is p_t x q packed by launch_pack_b with kpad_t (multiple of 16,

@@ -123,3 +123,23 @@ def grad_case(n=1 << 20, k0=64, k=32, seed_cfg=5):
     GQ = np.ascontiguousarray(gaussian(g, (n, k)))
     GR = np.ascontiguousarray(gaussian(g, (k, k)))
     return V, A, GQ, GR
+
+
+def batched_gpu(count=4096, device="cuda", seed_cfg=4):
+    """The batched workload generated on a GPU with torch (input generation
+    only): the shapes of ``batched_shapes``, Gaussian A, and V the Q factor of
+    a Gaussian matrix by two rounds of Cholesky QR (orthonormal to ~1e-15 for
+    these well-conditioned matrices).  Returns a list of (V, A) tensors."""
+    import torch
+    shapes = batched_shapes(count, seed_cfg)
+    g = torch.Generator(device=device).manual_seed(BASE_SEED + seed_cfg)
+    out = []
+    for (n, k0, k) in shapes:
+        X = torch.randn(n, k0, dtype=torch.float64, device=device, generator=g)
+        for _ in range(2):
+            G = X.T.contiguous() @ X
+            Lc = torch.linalg.cholesky(G)
+            X = torch.linalg.solve_triangular(Lc, X.T.contiguous(), upper=False).T.contiguous()
+        A = torch.randn(n, k, dtype=torch.float64, device=device, generator=g)
+        out.append((X, A))
+    return out
