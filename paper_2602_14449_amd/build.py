@@ -18,8 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtho.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "k_lowp.hip", "k_batched.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
-           "tho_backward.cpp", "tho_batched.cpp"]
+SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "k_lowp.hip", "k_batched.hip", "k_complex.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
+           "tho_backward.cpp", "tho_batched.cpp", "tho_complex.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -213,6 +213,12 @@ int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, con
     if (!bytes) return set_err(-6, "bytes must not be NULL");
     const int panel = opts ? opts->panel : 0;
     if (panel < THO_PANEL_F64 || panel > THO_PANEL_BF16) return set_err(-5, "unknown panel precision");
+    if (dtype == THO_C128) {
+        if (!zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
+        if (panel != THO_PANEL_F64) return set_err(THO_E_UNSUPPORTED, "reduced-precision panels are real only");
+        *bytes = ztwo_stage_bytes(n, k0, k);
+        return 0;
+    }
     *bytes = two_stage_bytes(n, k0, k, panel);
     return 0;
 }
@@ -222,11 +228,22 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
                   int64_t lds, const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
-    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented");
     const int panel = opts ? opts->panel : 0;
     if (opts && (opts->p_choice != THO_P_QR || opts->flags != 0))
         return set_err(THO_E_UNSUPPORTED, "only p_choice=THO_P_QR without flags is implemented");
     if (panel < THO_PANEL_F64 || panel > THO_PANEL_BF16) return set_err(-15, "unknown panel precision");
+    if (dtype == THO_C128) {
+        if (!zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
+        if (panel != THO_PANEL_F64) return set_err(THO_E_UNSUPPORTED, "reduced-precision panels are real only");
+        if (k == 0) return 0;
+        if ((rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds))) return rc;
+        for (const void* p : {V_, A_, (const void*)Q_, (const void*)R_, (const void*)S_})
+            if (p && ((uintptr_t)p & 15)) return set_err(-5, "complex matrices must be 16-byte aligned");
+        if (!ws) return set_err(-16, "workspace is NULL");
+        if (ws_bytes < ztwo_stage_bytes(n, k0, k)) return set_err(THO_E_WORKSPACE, "workspace too small");
+        return run_ztwo_stage(n, k0, k, (const dcplx*)V_, ldv, (const dcplx*)A_, lda, (dcplx*)Q_, ldq, (dcplx*)R_,
+                              ldr, (dcplx*)S_, lds, ws, (hipStream_t)stream);
+    }
     if (k == 0) return 0;
     rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds);
     if (rc) return rc;
@@ -242,6 +259,11 @@ int tho_hhqr_full_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, con
     if (!bytes) return set_err(-6, "bytes must not be NULL");
     (void)opts;
     if (k == 0) { *bytes = 0; return 0; }
+    if (dtype == THO_C128) {
+        if (!zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
+        *bytes = zhhqr_bytes(n, k0, k);
+        return 0;
+    }
     HhqrPlan H;
     make_hhqr_plan(n, k0, k, nullptr, H);
     *bytes = H.bytes;
@@ -253,12 +275,18 @@ int tho_hhqr_full(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
-    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented for tho_hhqr_full");
     if (opts && (opts->panel != THO_PANEL_F64 || opts->flags != 0))
         return set_err(THO_E_UNSUPPORTED, "tho_hhqr_full supports panel=THO_PANEL_F64 only");
+    if (dtype == THO_C128 && !zsupported(k0, k))
+        return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
     if (k == 0) return 0;
     if ((rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds))) return rc;
     if (!ws) return set_err(-16, "workspace is NULL");
+    if (dtype == THO_C128) {
+        if (ws_bytes < zhhqr_bytes(n, k0, k)) return set_err(THO_E_WORKSPACE, "workspace too small");
+        return run_zhhqr(n, k0, k, (const dcplx*)V_, ldv, (const dcplx*)A_, lda, (dcplx*)Q_, ldq, (dcplx*)R_, ldr,
+                         (dcplx*)S_, lds, ws, (hipStream_t)stream);
+    }
     HhqrPlan H;
     make_hhqr_plan(n, k0, k, nullptr, H);
     if (ws_bytes < H.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");

@@ -57,6 +57,11 @@ int tho_bcgs_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, int32_t 
     if (!bytes) return set_err(-8, "bytes must not be NULL");
     (void)opts;
     if (k == 0) { *bytes = 0; return 0; }
+    if (dtype == THO_C128) {
+        if (!zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
+        *bytes = zbcgs_bytes(n, k0, k);
+        return 0;
+    }
     BcgsPlan P;
     make_bcgs_plan(n, k0, k, nullptr, P);
     *bytes = P.bytes;
@@ -68,13 +73,19 @@ int tho_bcgs(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V_, in
              int32_t rounds, const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
-    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "only THO_F64 is implemented for tho_bcgs");
     if (opts && (opts->panel != THO_PANEL_F64 || opts->flags != 0))
         return set_err(THO_E_UNSUPPORTED, "tho_bcgs supports panel=THO_PANEL_F64 only");
     if ((rc = check_pr(proj, rounds, 15, 16))) return rc;
+    if (dtype == THO_C128 && !zsupported(k0, k))
+        return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
     if (k == 0) return 0;
     if ((rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds))) return rc;
     if (!ws) return set_err(-18, "workspace is NULL");
+    if (dtype == THO_C128) {
+        if (ws_bytes < zbcgs_bytes(n, k0, k)) return set_err(THO_E_WORKSPACE, "workspace too small");
+        return run_zbcgs(n, k0, k, (const dcplx*)V_, ldv, (const dcplx*)A_, lda, (dcplx*)Q_, ldq, (dcplx*)R_, ldr,
+                         (dcplx*)S_, lds, proj, rounds, ws, (hipStream_t)stream);
+    }
     BcgsPlan P;
     make_bcgs_plan(n, k0, k, nullptr, P);
     if (ws_bytes < P.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");

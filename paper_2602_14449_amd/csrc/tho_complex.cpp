@@ -1,0 +1,337 @@
+// Complex (complex128) two-stage orthogonalization, BCGS and full
+// Householder QR: Algorithm 1 with the second choice of P in complex
+// arithmetic (conjugate transposes throughout).
+//
+// Panel products run on the real FP64 MFMA kernels through real views of the
+// interleaved data: a complex n x p matrix is a real n x 2p matrix whose
+// columns alternate re, im.
+//   X^H Y:      the real reduction X_ri^T Y_ri (2p x 2q) and a re/im combine;
+//   Y + X B:    the real row-streaming product with B in 2 x 2 real block
+//               form [[br, bi], [-bi, br]].
+// The Householder QR of the bottom block and the formation of Q_ are complex
+// kernels (k_complex.hip); unlike the real path the update A + V Z and the
+// term V N are separate passes over the rows.
+#include <algorithm>
+
+#include "tho_host.h"
+
+using namespace tho;
+
+namespace {
+
+constexpr int ZMAX_K0 = 64, ZMAX_K = 32;
+
+struct ZTsqrPlan {
+    int64_t m = 0;
+    int k = 0, KP = 16;
+    std::vector<LevelPlan> lv;
+    dcplx *Rtop = nullptr, *G0 = nullptr;
+    std::vector<dcplx*> Tt, stack;
+};
+
+dcplx* ztake(Carve& cv, size_t n) { return (dcplx*)cv.take(2 * n); }
+
+void ztsqr_plan(int64_t m0, int k, Carve& cv, ZTsqrPlan& T) {
+    T.m = m0;
+    T.k = k;
+    T.KP = k <= 16 ? 16 : 32;
+    T.lv.clear();
+    const int tb = ztsqr_tile_rows(T.KP);
+    int64_t m = m0;
+    for (int level = 0;; level++) {
+        int64_t nc = cdiv(m, tb);
+        if (level == 0) nc = std::min<int64_t>(nc, 512);
+        nc = std::max<int64_t>(1, std::min<int64_t>(nc, m / std::max(1, k)));
+        T.lv.push_back({m, (int)nc, (int)cdiv(cdiv(m, nc), tb)});
+        if (nc == 1) break;
+        m = nc * k;
+    }
+    const size_t kk = (size_t)T.KP * T.KP;
+    T.Rtop = ztake(cv, kk);
+    T.G0 = ztake(cv, kk);
+    T.Tt.assign(T.lv.size(), nullptr);
+    T.stack.assign(T.lv.size(), nullptr);
+    for (size_t l = 0; l < T.lv.size(); l++) {
+        T.Tt[l] = ztake(cv, (size_t)T.lv[l].nchunk * T.lv[l].maxtiles * kk);
+        if (l >= 1) T.stack[l] = ztake(cv, (size_t)T.lv[l].m * T.KP);
+    }
+}
+
+std::vector<ZLevel> ztsqr_levels(const ZTsqrPlan& T, const dcplx* X, int64_t ldx, dcplx* Y, int64_t ldy) {
+    const int nl = (int)T.lv.size();
+    std::vector<ZLevel> Ls(nl);
+    for (int l = 0; l < nl; l++) {
+        ZLevel& L = Ls[l];
+        std::memset(&L, 0, sizeof(L));
+        L.m = T.lv[l].m;
+        L.k = T.k;
+        L.nchunk = T.lv[l].nchunk;
+        L.maxtiles = T.lv[l].maxtiles;
+        L.X = l == 0 ? X : T.stack[l];
+        L.ldx = l == 0 ? ldx : T.KP;
+        L.Y = l == 0 ? Y : T.stack[l];
+        L.ldy = l == 0 ? ldy : T.KP;
+        L.Tt = T.Tt[l];
+        L.Rnext = (l + 1 < nl) ? T.stack[l + 1] : T.Rtop;
+        L.ldrn = T.KP;
+        L.Gin = (l + 1 < nl) ? T.stack[l + 1] : T.G0;
+        L.ldg = T.KP;
+        L.gstride = (l + 1 < nl) ? T.k : 0;
+    }
+    return Ls;
+}
+
+// Householder QR of X (m x k) into explicit Q_ (in Y) and R (nonnegative
+// real diagonal); Y may equal X.
+int ztsqr(const ZTsqrPlan& T, const dcplx* X, int64_t ldx, dcplx* Y, int64_t ldy, dcplx* R, int64_t ldr,
+          hipStream_t st) {
+    std::vector<ZLevel> Ls = ztsqr_levels(T, X, ldx, Y, ldy);
+    const int nl = (int)Ls.size();
+    for (int l = 0; l < nl; l++) PROF(l == 0 ? "zleaf_l0" : "zleaf_up", st, launch_zleaf(T.KP, Ls[l], st));
+    PROF("zfinish_r", st, launch_zfinish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
+    for (int l = nl - 1; l >= 0; l--) PROF(l == 0 ? "zform_l0" : "zform_up", st, launch_zform(T.KP, Ls[l], st));
+    return 0;
+}
+
+// Complex reduction out (p x q, ld ldo) = sign * X^H Y over nrows rows.
+struct ZXty {
+    XtyPlan xp;
+    double *part, *raw;
+    int P2, Q2;  // padded real view sizes
+};
+
+void zxty_plan(int64_t nrows, int p, int q, Carve& cv, ZXty& Z) {
+    Z.xp = xty_plan(nrows);
+    Z.P2 = k0p_of(2 * p);
+    Z.Q2 = kp_of(2 * q);
+    Z.part = cv.take((size_t)Z.xp.nblk * Z.P2 * Z.Q2);
+    Z.raw = cv.take((size_t)Z.P2 * Z.Q2);
+}
+
+int zxty(const ZXty& Z, int64_t nrows, const dcplx* X, int64_t ldx, int p, const dcplx* Y, int64_t ldy, int q,
+         double sign, dcplx* out, int64_t ldo, hipStream_t st) {
+    int rc = xty(Z.xp, nrows, (const double*)X, 2 * ldx, 2 * p, (const double*)Y, 2 * ldy, 2 * q, Z.part, Z.raw, st,
+                 "xty_partial");
+    if (rc) return rc;
+    PROF("zcombine", st, launch_zcombine(p, q, Z.raw, Z.Q2, sign, out, ldo, st));
+    return 0;
+}
+
+// Out (nrows x q) = X + Y B with complex B (p x q, ld ldb) scaled by sign.
+struct ZRows {
+    double *exp, *pk;
+};
+
+void zrows_plan(int p, int q, Carve& cv, ZRows& Z) {
+    Z.exp = cv.take((size_t)4 * std::max(p, 1) * std::max(q, 1));
+    Z.pk = cv.take((size_t)k0p_of(2 * p) * rows_gemm_qp(2 * q) + 64);
+}
+
+int zrows(const ZRows& Z, int64_t nrows, const dcplx* X, int64_t ldx, dcplx* Out, int64_t ldo, const dcplx* Y,
+          int64_t ldy, int p, const dcplx* B, int64_t ldb, int q, double sign, hipStream_t st) {
+    const int kpad = k0p_of(2 * p), qp = rows_gemm_qp(2 * q);
+    PROF("zexpand", st, launch_zexpand(p, q, B, ldb, sign, Z.exp, st));
+    PROF("pack_b", st, launch_pack_b(2 * p, 2 * q, Z.exp, 2 * q, 0, 1.0, kpad, qp, Z.pk, st));
+    RowsGemm g{};
+    g.nrows = nrows;
+    g.X = (const double*)X;
+    g.ldx = 2 * ldx;
+    g.Out = (double*)Out;
+    g.ldo = 2 * ldo;
+    g.q = 2 * q;
+    g.nterm = 1;
+    g.t[0] = {(const double*)Y, 2 * ldy, 2 * p, kpad, Z.pk};
+    PROF("rows_gemm", st, launch_rows_gemm(g, st));
+    return 0;
+}
+
+struct ZPlan {
+    ZTsqrPlan ts;
+    ZXty xa, xg;
+    ZRows rz, rn;
+    dcplx *Pm, *Tm, *C, *Z, *A1t, *N;
+    size_t bytes;
+};
+
+void make_zplan(int64_t n, int64_t k0, int64_t k, void* ws, ZPlan& P) {
+    Carve cv(ws);
+    ztsqr_plan(n - k0, (int)k, cv, P.ts);
+    P.Pm = P.Tm = P.C = P.Z = P.A1t = P.N = nullptr;
+    if (k0 > 0) {
+        zxty_plan(n, (int)k0, (int)k, cv, P.xa);
+        zxty_plan(n - k0, (int)k0, (int)k, cv, P.xg);
+        zrows_plan((int)k0, (int)k, cv, P.rz);
+        zrows_plan((int)k0, (int)k, cv, P.rn);
+        P.Pm = ztake(cv, (size_t)k0 * k0);
+        P.Tm = ztake(cv, (size_t)k0 * k0);
+        P.C = ztake(cv, (size_t)k0 * k);
+        P.Z = ztake(cv, (size_t)k0 * k);
+        P.A1t = ztake(cv, (size_t)k0 * k);
+        P.N = ztake(cv, (size_t)k0 * k);
+    }
+    P.bytes = cv.bytes();
+}
+
+}  // namespace
+
+namespace tho {
+
+bool zsupported(int64_t k0, int64_t k) { return k0 <= ZMAX_K0 && k <= ZMAX_K; }
+
+size_t ztwo_stage_bytes(int64_t n, int64_t k0, int64_t k) {
+    if (k == 0) return 0;
+    ZPlan P;
+    make_zplan(n, k0, k, nullptr, P);
+    return P.bytes;
+}
+
+int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda,
+                   dcplx* Q, int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st) {
+    int rc = 0;
+    ZPlan P;
+    make_zplan(n, k0, k, ws, P);
+    const int ik = (int)k, ik0 = (int)k0;
+    const int64_t m = n - k0;
+    const dcplx* X0 = A + k0 * lda;  // bottom block, or its update
+    int64_t ldx0 = lda;
+    if (k0 > 0) {
+        // P = -Q1, T = I + R1^H from V_top = Q1 R1 (real diag R1 >= 0)
+        PROF("zqr_top", st, launch_zqr_top(ik0, V, ldv, P.Pm, P.Tm, st));
+        // W^H A = P^H A_top - V^H A ;  Z = T^{-H} W^H A
+        if ((rc = zxty(P.xa, n, V, ldv, ik0, A, lda, ik, 1.0, P.C, k, st))) return rc;
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 2, A, lda, 0, -1, 0, P.C, k, P.Z, k, st));
+        PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 2, P.Z, k, st));
+        // A1_top = A_top - (P - V_top) Z ;  S = P^H A1_top
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.Z, k, 0, 1, 0, A, lda, P.A1t, k, st));
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, V, ldv, 0, P.Z, k, 0, 1, 0, P.A1t, k, P.A1t, k, st));
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 2, P.A1t, k, 0, 0, 0, nullptr, 0, S, lds, st));
+        // A1_low = A_low + V_low Z  (into the Q buffer)
+        if ((rc = zrows(P.rz, m, A + k0 * lda, lda, Q + k0 * ldq, ldq, V + k0 * ldv, ldv, ik0, P.Z, k, ik, 1.0, st)))
+            return rc;
+        X0 = Q + k0 * ldq;
+        ldx0 = ldq;
+    }
+    // A1_low = Q_ R (Householder, chunked)
+    if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st))) return rc;
+    if (k0 > 0) {
+        // G = W^H [0; Q_] = -V_low^H Q_ ;  N = T^{-1} G
+        if ((rc = zxty(P.xg, m, V + k0 * ldv, ldv, ik0, Q + k0 * ldq, ldq, ik, -1.0, P.N, k, st))) return rc;
+        PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 0, P.N, k, st));
+        // Q_low = Q_ + V_low N ;  Q_top = -(P - V_top) N
+        if ((rc = zrows(P.rn, m, Q + k0 * ldq, ldq, Q + k0 * ldq, ldq, V + k0 * ldv, ldv, ik0, P.N, k, ik, 1.0, st)))
+            return rc;
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.N, k, 0, 0, 0, nullptr, 0, Q, ldq, st));
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, V, ldv, 0, P.N, k, 0, 1, 0, Q, ldq, Q, ldq, st));
+    }
+    return 0;
+}
+
+// ---- complex BCGS (same rounds/projections as the real tho_bcgs)
+struct ZBcgsPlan {
+    ZTsqrPlan ts;
+    ZXty xc;
+    ZRows rc;
+    dcplx *C, *Sr, *Rr, *Rtmp;
+    size_t bytes;
+};
+
+static void make_zbcgs_plan(int64_t n, int64_t k0, int64_t k, void* ws, ZBcgsPlan& P) {
+    Carve cv(ws);
+    ztsqr_plan(n, (int)k, cv, P.ts);
+    P.C = P.Sr = nullptr;
+    if (k0 > 0) {
+        zxty_plan(n, (int)k0, (int)k, cv, P.xc);
+        zrows_plan((int)k0, (int)k, cv, P.rc);
+        P.C = ztake(cv, (size_t)k0 * k);
+        P.Sr = ztake(cv, (size_t)k0 * k);
+    }
+    P.Rr = ztake(cv, (size_t)k * k);
+    P.Rtmp = ztake(cv, (size_t)k * k);
+    P.bytes = cv.bytes();
+}
+
+size_t zbcgs_bytes(int64_t n, int64_t k0, int64_t k) {
+    if (k == 0) return 0;
+    ZBcgsPlan P;
+    make_zbcgs_plan(n, k0, k, nullptr, P);
+    return P.bytes;
+}
+
+int run_zbcgs(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
+              int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, int proj, int rounds, void* ws,
+              hipStream_t st) {
+    int rc = 0;
+    ZBcgsPlan P;
+    make_zbcgs_plan(n, k0, k, ws, P);
+    const int ik = (int)k, ik0 = (int)k0;
+    const dcplx* X = A;
+    int64_t ldx = lda;
+    for (int r = 0; r < rounds; r++) {
+        if (k0 > 0) {
+            for (int p = 0; p < proj; p++) {
+                if ((rc = zxty(P.xc, n, V, ldv, ik0, X, ldx, ik, 1.0, P.C, k, st))) return rc;
+                if ((rc = zrows(P.rc, n, X, ldx, Q, ldq, V, ldv, ik0, P.C, k, ik, -1.0, st))) return rc;
+                X = Q;
+                ldx = ldq;
+                // S_r (+)= C on the interleaved real view (k0 x 2k)
+                PROF("small_ew", st, launch_small_ew(ik0, 2 * ik, p == 0 ? 0.0 : 1.0, p == 0 ? nullptr : (double*)P.Sr,
+                                                     2 * k, 0, 1.0, (const double*)P.C, 2 * k, 0, 0.0, 0,
+                                                     (double*)P.Sr, 2 * k, st));
+            }
+        }
+        if ((rc = ztsqr(P.ts, X, ldx, Q, ldq, P.Rr, k, st))) return rc;
+        X = Q;
+        ldx = ldq;
+        if (r == 0) {
+            if (k0 > 0)
+                PROF("zgemm", st, launch_zgemm(ik0, ik, 0, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 1, 0, P.Sr, k, S, lds,
+                                               st));
+            PROF("zgemm", st, launch_zgemm(ik, ik, 0, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 1, 0, P.Rr, k, R, ldr, st));
+        } else {
+            if (k0 > 0)
+                PROF("zgemm", st, launch_zgemm(ik0, ik, ik, 1, 0, P.Sr, k, 0, R, ldr, 0, 1, 0, S, lds, S, lds, st));
+            PROF("zgemm", st, launch_zgemm(ik, ik, ik, 1, 0, P.Rr, k, 0, R, ldr, 0, 0, 0, nullptr, 0, P.Rtmp, k, st));
+            PROF("zgemm", st, launch_zgemm(ik, ik, 0, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 1, 0, P.Rtmp, k, R, ldr, st));
+        }
+    }
+    return 0;
+}
+
+// ---- complex full Householder QR of [V, A]: Algorithm 4 over 32-column panels
+struct ZHhqrPlan {
+    dcplx *Qv, *Rtmp, *Stmp;
+    void* sub;
+    size_t bytes;
+};
+
+static void make_zhhqr_plan(int64_t n, int64_t k0, int64_t k, void* ws, ZHhqrPlan& H) {
+    Carve cv(ws);
+    H.Qv = ztake(cv, (size_t)n * std::max<int64_t>(k0, 1));
+    H.Rtmp = ztake(cv, 32 * 32);
+    H.Stmp = ztake(cv, (size_t)std::max<int64_t>(k0, 1) * 32);
+    size_t sub = ztwo_stage_bytes(n, k0, k);
+    for (int64_t c = 0; c < k0; c += 32) sub = std::max(sub, ztwo_stage_bytes(n, c, std::min<int64_t>(32, k0 - c)));
+    H.sub = cv.take(sub / sizeof(double) + 1);
+    H.bytes = cv.bytes();
+}
+
+size_t zhhqr_bytes(int64_t n, int64_t k0, int64_t k) {
+    if (k == 0) return 0;
+    ZHhqrPlan H;
+    make_zhhqr_plan(n, k0, k, nullptr, H);
+    return H.bytes;
+}
+
+int run_zhhqr(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
+              int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st) {
+    ZHhqrPlan H;
+    make_zhhqr_plan(n, k0, k, ws, H);
+    for (int64_t c = 0; c < k0; c += 32) {
+        const int64_t w = std::min<int64_t>(32, k0 - c);
+        int rc = run_ztwo_stage(n, c, w, H.Qv, k0, V + c, ldv, H.Qv + c, k0, H.Rtmp, 32, H.Stmp, 32, H.sub, st);
+        if (rc) return rc;
+    }
+    return run_ztwo_stage(n, k0, k, H.Qv, k0, A, lda, Q, ldq, R, ldr, S, lds, H.sub, st);
+}
+
+}  // namespace tho

@@ -124,4 +124,17 @@ XtyPlan xty_plan(int64_t nrows);
 int xty(const XtyPlan& xp, int64_t nrows, const double* X, int64_t ldx, int p, const double* Y, int64_t ldy, int q,
         double* part, double* out, hipStream_t st, const char* name, int panel = 0);
 
+// ---- complex path (tho_complex.cpp); k0 <= 64, k <= 32
+bool zsupported(int64_t k0, int64_t k);
+size_t ztwo_stage_bytes(int64_t n, int64_t k0, int64_t k);
+int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda,
+                   dcplx* Q, int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st);
+size_t zbcgs_bytes(int64_t n, int64_t k0, int64_t k);
+int run_zbcgs(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
+              int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, int proj, int rounds, void* ws,
+              hipStream_t st);
+size_t zhhqr_bytes(int64_t n, int64_t k0, int64_t k);
+int run_zhhqr(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
+              int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st);
+
 }  // namespace tho

@@ -75,6 +75,45 @@ hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* N
 hipError_t launch_small_ew(int M, int N, double a, const double* X, int64_t ldx, int tx, double b, const double* Y,
                            int64_t ldy, int ty, double c, int mode, double* D, int64_t ldd, hipStream_t st);
 
+// ---- complex path (k_complex.hip): interleaved (re, im) doubles
+struct dcplx {
+    double re, im;
+};
+// One level of the complex chunked TSQR (leaf) / formation (form); the same
+// roles as TsqrLevel without the fused V products.
+struct ZLevel {
+    int64_t m;
+    int k, nchunk, maxtiles, pad;
+    const dcplx* X;
+    int64_t ldx;
+    dcplx* Y;
+    int64_t ldy;
+    dcplx* Tt;     // [nchunk * maxtiles][KP * KP]
+    dcplx* Rnext;  // chunk R factors, rows c*k .., ld ldrn
+    int64_t ldrn;
+    const dcplx* Gin;
+    int64_t ldg;
+    int64_t gstride;
+};
+int ztsqr_tile_rows(int kp);
+hipError_t launch_zleaf(int kp, const ZLevel& L, hipStream_t st);  // kp in {16, 32}
+hipError_t launch_zform(int kp, const ZLevel& L, hipStream_t st);
+hipError_t launch_zqr_top(int n, const void* Vt, int64_t ldv, void* P, void* T, hipStream_t st);  // n <= 64
+// D = alpha op(A) op(B) + beta C (op: 0 none, 1 transpose, 2 conjugate transpose)
+hipError_t launch_zgemm(int M, int N, int K, double ar, double ai, const void* A, int64_t lda, int opa, const void* B,
+                        int64_t ldb, int opb, double br, double bi, const void* C, int64_t ldc, void* D, int64_t ldd,
+                        hipStream_t st);
+// In-place solve with lower-triangular L: mode 0 L X = B, mode 2 L^H X = B.
+hipError_t launch_ztrsm(int n, int m, const void* L, int64_t ldl, int mode, void* B, int64_t ldb, hipStream_t st);
+// out = sign * X^H Y from the real-view reduction Cr = X_ri^T Y_ri (2p x 2q).
+hipError_t launch_zcombine(int p, int q, const double* Cr, int64_t ldc, double sign, void* out, int64_t ldo,
+                           hipStream_t st);
+// Real 2 x 2 block form (2p x 2q, ld 2q) of sign * B (p x q complex).
+hipError_t launch_zexpand(int p, int q, const void* B, int64_t ldb, double sign, double* dst, hipStream_t st);
+hipError_t launch_zfinish_r(int k, int KP, const void* Rin, int64_t ldri, void* Rout, int64_t ldr, void* G0,
+                            hipStream_t st);
+hipError_t launch_zcopy(int64_t M, int N, const void* src, int64_t lds, void* dst, int64_t ldd, hipStream_t st);
+
 // One problem of the batched path (k_batched.hip): inputs/outputs as in
 // tho_two_stage plus its own workspace pieces (all device pointers).
 struct BatchedInst {
