@@ -14,6 +14,8 @@ Other workloads (--workload):
             k = 32, Gaussian loss weights G_Q, G_R
   batched   4096 problems (n ~ U[2048, 65536], k0 in {8,16,32,64},
             k in {4,8,16}) in one graph-captured persistent launch
+  complex   complex128, n = 2^20, k0 = 64, k = 32, A = V C + 1e-10 G
+            (cond([V, A]) ~ 1e10), with BCGS and full Householder QR beside it
 
 value   = algorithmic bytes / time.  Two-stage: B_alg = 8 n (3 k0 + 4 k) (V
           and A streamed once in each of the three phases their dependences
@@ -40,7 +42,7 @@ import time
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 HERE = os.path.dirname(os.path.abspath(__file__))
-WORKLOADS = ["graded", "graded-f32x2", "graded-bf16", "grad", "batched"]
+WORKLOADS = ["graded", "graded-f32x2", "graded-bf16", "grad", "batched", "complex"]
 
 
 def parse():
@@ -94,10 +96,10 @@ def gram_loss(V, Q):
     G = None
     for i in range(0, n, 1 << 18):
         blk = torch.cat([V[i:i + (1 << 18)], Q[i:i + (1 << 18)]], 1)
-        gg = blk.T.contiguous() @ blk
+        gg = blk.mH.contiguous() @ blk
         G = gg if G is None else G + gg
     Gm = G.cpu().numpy() - np.eye(G.shape[0])
-    return float(np.max(np.abs(np.linalg.eigvalsh(0.5 * (Gm + Gm.T)))))
+    return float(np.max(np.abs(np.linalg.eigvalsh(0.5 * (Gm + Gm.conj().T)))))
 
 
 def rel_res(V, A, Q, R, S):
@@ -108,8 +110,8 @@ def rel_res(V, A, Q, R, S):
         sl = slice(i, i + (1 << 18))
         eb = A[sl] - V[sl] @ S - Q[sl] @ R
         ab = A[sl]
-        x = eb.T.contiguous() @ eb
-        y = ab.T.contiguous() @ ab
+        x = eb.mH.contiguous() @ eb
+        y = ab.mH.contiguous() @ ab
         ge = x if ge is None else ge + x
         ga = y if ga is None else ga + y
     return float(np.sqrt(np.max(np.linalg.eigvalsh(ge.cpu().numpy())) /
@@ -387,6 +389,79 @@ def run_batched(a):
     return out
 
 
+def run_complex(a):
+    import torch
+    import paper_2602_14449_amd as tho
+    n = a.n or (1 << 20)
+    k0 = a.k0 if a.k0 is not None else 64
+    k = a.k or 32
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(260214449 + 2)
+    c128 = torch.complex128
+
+    def cn(*shape):
+        return torch.randn(*shape, dtype=c128, device=dev, generator=g)
+    V, _ = torch.linalg.qr(cn(n, k0))
+    V = V.contiguous()
+    A = (V @ cn(k0, k) + 1e-10 * cn(n, k)).contiguous()
+    Q = torch.empty(n, k, dtype=c128, device=dev)
+    R = torch.empty(k, k, dtype=c128, device=dev)
+    S = torch.empty(k0, k, dtype=c128, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ms, prof = time_steps(lambda: tho.two_stage(V, A, out=(Q, R, S)), a.steps, a.warmup, stream)
+    B_alg = 16.0 * n * (3 * k0 + 4 * k)
+    gbs = B_alg / (ms * 1e-3) / 1e9
+    out = base_line(a, "two-stage orth GB/s (% HBM peak) vs full HHQR of [V,A]; orth loss vs FP64", gbs, ms,
+                    "c128", "complex: complex128 two-stage, n=%d, k0=%d, k=%d, A = V C + 1e-10 G" % (n, k0, k),
+                    {"n": n, "k0": k0, "k": k})
+    out["pct_hbm_peak"] = round(100.0 * gbs / HBM_PEAK_GBS, 2)
+
+    def model(nm):
+        m = n - k0
+        if nm == "zleaf_l0":   # complex Householder of the m x k block: read, write vectors
+            return 16.0 * m * 2 * k, 8.0 * m * k * k
+        if nm == "zform_l0":
+            return 16.0 * m * 2 * k, 8.0 * m * k * k
+        if nm == "rows_gemm":  # A + V Z and Q_ + V N (average of the two)
+            return 16.0 * m * (k0 + 2 * k), 8.0 * m * k0 * k
+        if nm == "xty_partial":
+            return 16.0 * n * (k0 + k), 8.0 * n * k0 * k
+        return None
+    dname = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    out["roofline"] = roofline(prof, model, "hbm" if dname in ("rows_gemm", "xty_partial") else "mfma")
+    out["kernels_ms_per_step"] = {kn: round(v[0] / a.steps, 4) for kn, v in
+                                  sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    if not a.no_check:
+        out["accuracy"] = {"orth_loss": gram_loss(V, Q), "rel_residual": rel_res(V, A, Q, R, S)}
+        comp = {}
+        for name, fn in [("hhqr_full", lambda: tho.hhqr_full(V, A, out=(Q, R, S))),
+                         ("bcgs_1_1", lambda: tho.bcgs(V, A, 1, 1, out=(Q, R, S))),
+                         ("bcgs_1_2", lambda: tho.bcgs(V, A, 1, 2, out=(Q, R, S)))]:
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            comp[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 3), "orth_loss": gram_loss(V, Q),
+                          "rel_residual": rel_res(V, A, Q, R, S)}
+        out["comparisons"] = comp
+    if not a.no_cpu_baseline:
+        from oracle import two_stage as oracle_two_stage
+        ns = min(a.cpu_rows, n) // 4
+        Vh, Ah = V[:ns].cpu().numpy(), A[:ns].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle_two_stage(Vh, Ah)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(16.0 * ns * (3 * k0 + 4 * k) / t / 1e9, 4), "unit": "GB/s",
+                               "cores": int(threads_used()), "kind": "oracle",
+                               "sample": "complex workload rows 0..%d (first rows of the same V, A), k0=%d, k=%d; "
+                                         "one oracle run, %.1f s" % (ns, k0, k, t)}
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -403,6 +478,8 @@ def main():
         out = run_graded(a, "bf16")
     elif a.workload == "grad":
         out = run_grad(a)
+    elif a.workload == "complex":
+        out = run_complex(a)
     else:
         out = run_batched(a)
     print(json.dumps(out), flush=True)

@@ -70,9 +70,13 @@ typedef struct {
 #define THO_E_UNSUPPORTED (-102)
 
 /* Largest supported k0 and k (the k0 x k0 and k x k factorizations run
- * inside one workgroup; see the design notes). */
+ * inside one workgroup).  THO_C128 supports k0 <= 64 and k <= 32
+ * (THO_E_UNSUPPORTED beyond); reduced-precision panels, the adjoint and the
+ * batched path are real (THO_F64) only. */
 #define THO_MAX_K0 128
 #define THO_MAX_K  64
+#define THO_MAX_K0_C128 64
+#define THO_MAX_K_C128  32
 
 /* Bytes of device workspace tho_two_stage needs for these sizes (opts may be
  * NULL for defaults).  Returns 0 or -i like the other calls. */
