@@ -141,32 +141,51 @@ __global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __
     D[(int64_t)i * ldd + j] = r;
 }
 
-// In-place solve with a lower-triangular L (n x n, ld ldl) on B (n x m):
+// In-place solve with a lower-triangular L (n x n, ld ldl, n <= 128) on
+// B (n x m):
 //   trans == 0:  L X = B   (forward substitution)
 //   trans == 1:  L^T X = B (backward substitution; L^T is upper)
-// One workgroup; B staged in LDS (n*m doubles, dynamic).
-__global__ __launch_bounds__(1024) void k_trsm_lower(int n, int m, const double* __restrict__ L,
-                                                     int64_t ldl, int trans, double* B,
-                                                     int64_t ldb) {
+// One 64-lane workgroup per column of B (the columns are independent).  L is
+// staged in LDS (row stride n + 1); lane l keeps rows l and l + 64 of its
+// column in registers, so each row step is two LDS loads, a VALU wave sum
+// and one update by the owning lane -- no barriers after the staging.
+constexpr int TRSM_NMAX = 128;
+
+__global__ __launch_bounds__(64) void k_trsm_lower(int n, int m, const double* __restrict__ L,
+                                                   int64_t ldl, int trans, double* B, int64_t ldb) {
     extern __shared__ double sm[];
-    double* Bs = sm;  // n x m
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < n * m; e += nt) Bs[e] = B[(int64_t)(e / m) * ldb + (e % m)];
+    const int ld = n + 1;
+    double* Ls = sm;  // n x ld
+    const int l = threadIdx.x, j = blockIdx.x;
+    for (int e = l; e < n * n; e += 64) {
+        const int i = e / n, p = e % n;
+        Ls[i * ld + p] = (p <= i) ? L[(int64_t)i * ldl + p] : 0.0;
+    }
+    double x0 = (l < n) ? B[(int64_t)l * ldb + j] : 0.0;
+    double x1 = (l + 64 < n) ? B[(int64_t)(l + 64) * ldb + j] : 0.0;
     __syncthreads();
     for (int it = 0; it < n; it++) {
         const int i = trans ? (n - 1 - it) : it;
-        if (tid < m) Bs[i * m + tid] /= L[(int64_t)i * ldl + i];
-        __syncthreads();
-        const int cnt = trans ? i : (n - 1 - i);
-        for (int e = tid; e < cnt * m; e += nt) {
-            const int r = e / m, c = e % m;
-            const int pr = trans ? r : (i + 1 + r);
-            const double lv = trans ? L[(int64_t)i * ldl + pr] : L[(int64_t)pr * ldl + i];
-            Bs[pr * m + c] -= lv * Bs[i * m + c];
+        // terms p < i (forward: L[i][p]) or p > i (backward: L[p][i])
+        // LDS indices are clamped into the staged n x n block (values masked)
+        const int r0 = (l < n) ? l : n - 1, r1 = (l + 64 < n) ? l + 64 : n - 1;
+        double t0, t1;
+        if (trans) {
+            const double a0 = Ls[r0 * ld + i], a1 = Ls[r1 * ld + i];
+            t0 = (l > i && l < n) ? a0 * x0 : 0.0;
+            t1 = (l + 64 > i && l + 64 < n) ? a1 * x1 : 0.0;
+        } else {
+            const double a0 = Ls[i * ld + r0], a1 = Ls[i * ld + r1];
+            t0 = (l < i) ? a0 * x0 : 0.0;
+            t1 = (l + 64 < i) ? a1 * x1 : 0.0;
         }
-        __syncthreads();
+        const double s = sum_wave_valu(t0 + t1);
+        const double d = Ls[i * ld + i];
+        if (l == i) x0 = (x0 - s) / d;
+        if (l + 64 == i) x1 = (x1 - s) / d;
     }
-    for (int e = tid; e < n * m; e += nt) B[(int64_t)(e / m) * ldb + (e % m)] = Bs[e];
+    if (l < n) B[(int64_t)l * ldb + j] = x0;
+    if (l + 64 < n) B[(int64_t)(l + 64) * ldb + j] = x1;
 }
 
 __global__ __launch_bounds__(1024) void k_qr_top(int n, const double* __restrict__ Vt, int64_t ldv,
@@ -308,14 +327,16 @@ hipError_t launch_small_gemm(int M, int N, int K, double alpha, const double* A,
 hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int trans, double* B,
                              int64_t ldb, hipStream_t st) {
     if (n <= 0 || m <= 0) return hipSuccess;
-    const size_t shm = (size_t)n * m * sizeof(double);
+    if (n > TRSM_NMAX) return hipErrorInvalidValue;
+    const size_t shm = (size_t)n * (n + 1) * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_trsm_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void*)k_trsm_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_trsm_lower, dim3(1), dim3(1024), shm, st, n, m, L, ldl, trans, B, ldb);
+    hipLaunchKernelGGL(k_trsm_lower, dim3(m), dim3(64), shm, st, n, m, L, ldl, trans, B, ldb);
     return hipGetLastError();
 }
 
@@ -324,8 +345,9 @@ hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double
     const size_t shm = (size_t)qr_top_lds(n) * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_qr_top, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void*)k_qr_top, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
         attr = true;
     }
     hipLaunchKernelGGL(k_qr_top, dim3(1), dim3(1024), shm, st, n, Vt, ldv, P, T);

@@ -85,6 +85,28 @@ int check_io(int64_t k0, int64_t k, const void* V, int64_t ldv, const void* A, i
 
 namespace {
 
+// Side stream (default priority) and two events per host thread and device,
+// used to run the k0 x k0 QR concurrently with the first reduction.
+struct Fork {
+    bool ok = false;
+    hipStream_t side = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+Fork& fork_for_thread() {
+    thread_local std::vector<Fork> forks;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if ((int)forks.size() <= dev) forks.resize(dev + 1);
+    Fork& f = forks[dev];
+    if (!f.ok) {
+        f.ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&f.ev0, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&f.ev1, hipEventDisableTiming) == hipSuccess;
+    }
+    return f;
+}
+
 // Launch sequence of Algorithm 1 (second choice of P) on validated
 // arguments; ws holds at least two_stage_bytes(n, k0, k).
 int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv, const double* A, int64_t lda,
@@ -99,11 +121,18 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
     const size_t nk = (size_t)std::max(K0P, 16) * KP;
 
     if (k0 > 0) {
-        // P and T, second choice (§3.2): V_top = Q1 R1, P = -Q1, T = I + R1^T
-        PROF("qr_top", st, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, st));
-        // update of A, reduction: C = V^T A over all n rows
+        // P and T, second choice (§3.2): V_top = Q1 R1, P = -Q1, T = I + R1^T,
+        // on a side stream, concurrently with the reduction C = V^T A over
+        // all n rows (update of A); joined before the first use of P and T
+        Fork& f = fork_for_thread();
+        if (!f.ok) return set_err(THO_E_HIP, "could not create the side stream");
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        PROF("qr_top", f.side, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, f.side));
+        HIPCHK(hipEventRecord(f.ev1, f.side));
         rc = xty(P.xp, n, V, ldv, ik0, A, lda, ik, P.part, P.Cbuf, st, "xty_partial", panel);
         if (rc) return rc;
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
         // W^T A = P^T A_top - C ;  Z = T^{-T} (W^T A)
         PROF("fill", st, fill(P.Zbuf, (int64_t)nk, 0.0, st));
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.Cbuf, KP, P.Zbuf,

@@ -35,12 +35,82 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Row (within a 16-row block) of accumulator element v of lane l.
 __device__ __forceinline__ int drow(int l, int v) { return (l >> 4) + 4 * v; }
 
+// ---- cross-lane moves on VALU (no LDS crossbar)
+__device__ __forceinline__ unsigned dlo(double x) { return (unsigned)__double_as_longlong(x); }
+__device__ __forceinline__ unsigned dhi(double x) { return (unsigned)(__double_as_longlong(x) >> 32); }
+__device__ __forceinline__ double dmake(unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v_permlane16_swap with both operands x: every lane receives the pair
+// (value of its lane in the even 16-lane row, value in the odd row) of its
+// 32-lane half.
+struct dpair {
+    double even, odd;
+};
+__device__ __forceinline__ dpair pair16(double x) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(dlo(x), dlo(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(dhi(x), dhi(x), false, false);
+    return {dmake(lo[0], hi[0]), dmake(lo[1], hi[1])};
+}
+// v_permlane32_swap: (value in the lower 32-lane half, value in the upper half).
+__device__ __forceinline__ dpair pair32(double x) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(dlo(x), dlo(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(dhi(x), dhi(x), false, false);
+    return {dmake(lo[0], hi[0]), dmake(lo[1], hi[1])};
+}
+
 // Sum across the four 16-lane groups of a wavefront (lanes l, l^16, l^32,
-// l^48 end up with the same value).
+// l^48 end up with the same value, bitwise).
 __device__ __forceinline__ double sum_groups(double x) {
-    x += __shfl_xor(x, 16);
-    x += __shfl_xor(x, 32);
-    return x;
+    const dpair a = pair16(x);
+    const dpair b = pair32(a.even + a.odd);
+    return b.even + b.odd;
+}
+
+// Sum across the four lanes of a quad (DPP quad_perm).
+__device__ __forceinline__ double sum_quad(double x) {
+    const double y = dmake((unsigned)__builtin_amdgcn_mov_dpp((int)dlo(x), 0xB1, 0xF, 0xF, false),
+                           (unsigned)__builtin_amdgcn_mov_dpp((int)dhi(x), 0xB1, 0xF, 0xF, false));
+    x += y;
+    const double z = dmake((unsigned)__builtin_amdgcn_mov_dpp((int)dlo(x), 0x4E, 0xF, 0xF, false),
+                           (unsigned)__builtin_amdgcn_mov_dpp((int)dhi(x), 0x4E, 0xF, 0xF, false));
+    return x + z;
+}
+
+// Value of lane `lane` (wave-uniform) in every lane.
+__device__ __forceinline__ double bcast(double x, int lane) {
+    return dmake((unsigned)__builtin_amdgcn_readlane((int)dlo(x), lane),
+                 (unsigned)__builtin_amdgcn_readlane((int)dhi(x), lane));
+}
+
+// For a per-lane value x (lane l holding the entry of column l), the values
+// of lanes c, 16 + c, 32 + c, 48 + c with c = l % 16 (the four 16-column
+// blocks of column c), in every lane.
+__device__ __forceinline__ void gather_cols(double x, double (&out)[4]) {
+    const dpair a = pair16(x);      // rows (0, 1) or (2, 3) of my half
+    const dpair e = pair32(a.even);  // rows 0 and 2
+    const dpair o = pair32(a.odd);   // rows 1 and 3
+    out[0] = e.even;
+    out[1] = o.even;
+    out[2] = e.odd;
+    out[3] = o.odd;
+}
+
+// Full wavefront sum on VALU (DPP row rotations, then permlane swaps).  The
+// value is exact in every lane but may differ in the last bit between
+// lanes (each lane adds in its own order); use it from one lane only when
+// bitwise agreement matters.
+__device__ __forceinline__ double sum_wave_valu(double x) {
+#define THO_ROR(v, c)                                                                   \
+    dmake((unsigned)__builtin_amdgcn_mov_dpp((int)dlo(v), c, 0xF, 0xF, false),          \
+          (unsigned)__builtin_amdgcn_mov_dpp((int)dhi(v), c, 0xF, 0xF, false))
+    x += THO_ROR(x, 0x128);  // row_ror:8
+    x += THO_ROR(x, 0x124);  // row_ror:4
+    x += THO_ROR(x, 0x122);  // row_ror:2
+    x += THO_ROR(x, 0x121);  // row_ror:1
+#undef THO_ROR
+    return sum_groups(x);
 }
 
 // Full wavefront sum.

@@ -156,23 +156,29 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
             for (int ww = 0; ww < NW; ww++) dl += part[(pb * NW + ww) * KP + l];
             pl = PLAIN ? prow[pb * KP + l] : slot[j * LDT + l];
         }
-        const double sig2 = __shfl(dl, j);
-        const double alpha = __shfl(pl, j);
+        const double sig2 = bcast(dl, j);
+        const double alpha = bcast(pl, j);
         double beta = alpha, tau = 0.0, scale = 0.0;
         if (sig2 != 0.0) {
+            // one division: r = 1 / (beta (alpha - beta)) gives
+            // 1 / (alpha - beta) = beta r and tau = (beta - alpha) / beta = -(alpha - beta)^2 r
             const double nrm = sqrt(alpha * alpha + sig2);
             beta = (alpha < 0.0) ? nrm : -nrm;
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
+            const double amb = alpha - beta;
+            const double r = 1.0 / (beta * amb);
+            tau = -(amb * amb) * r;
+            scale = beta * r;
         }
         const double wl = pl + scale * dl;
         if (w == 0) {
             if (l < j) Gm[j * LDT + l] = wl;
             if (l == 0) taus[j] = tau;
         }
+        double wv4[4];
+        gather_cols(wl, wv4);
         double wv[CT];
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) wv[ct] = __shfl(wl, 16 * ct + cl);
+        for (int ct = 0; ct < CT; ct++) wv[ct] = wv4[ct];
         double u[RB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; rb++)
@@ -314,25 +320,46 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         PHASE_TS(t, 2);
         // compact-WY factor (H_0 ... H_{k-1} = I - U T U^T):
         //   T(i,i) = tau_i,  T(i,j) = -tau_j sum_{i<=p<j} T(i,p) u_p^T u_j
-        // Rows of T are independent; four lanes of one wavefront own a row and
-        // sweep its columns (no workgroup barrier).  Gm(j,p) = u_p^T u_j sits
-        // in the strict lower triangle of TG, T in the upper one.
+        // Rows of T are independent.  Four lanes own a row and keep its
+        // entries p = lane + 4 q in registers; step j reads row j of the Gram
+        // (Gm(j,p) = u_p^T u_j, strict lower triangle of TG; the same
+        // addresses for every row, so mostly broadcasts) and reduces over the
+        // four lanes with quad shuffles.  Entries p >= j of a row are still
+        // zero at step j, so no masking is needed.  T goes to the upper
+        // triangle of TG (disjoint from Gm).
         {
-            const int ti = tid >> 2, tq = tid & 3;
+            constexpr int NQ = KP / 4;
+            const int tq = tid & 3, ti = tid >> 2;  // 64 rows x 4 lanes
+            double Tr[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) Tr[q] = (tq + 4 * q == ti && ti < k) ? taus[ti] : 0.0;
+            for (int j = 1; j < k; j++) {
+                // all loads are in bounds (j, p < KP): issue them unconditionally
+                // and mask the values, four independent partial sums
+                double g[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; q++) g[q] = TG[j * LDT + tq + 4 * q];
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < NQ; q++) s4[q & 3] += Tr[q] * ((tq + 4 * q < j) ? g[q] : 0.0);
+                double sr = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                sr = sum_quad(sr);
+                if (j > ti && tq == (j & 3)) {
+                    const double v = -taus[j] * sr;
+#pragma unroll
+                    for (int q = 0; q < NQ; q++)
+                        if (q == (j >> 2)) Tr[q] = v;
+                }
+            }
             if (ti < k) {
-                if (tq == 0) TG[ti * LDT + ti] = taus[ti];
-                for (int j = ti + 1; j < k; j++) {
-                    double s = 0.0;
-                    for (int p = ti + tq; p < j; p += 4) s += TG[ti * LDT + p] * TG[j * LDT + p];
-                    s += __shfl_xor(s, 1);
-                    s += __shfl_xor(s, 2);
-                    if (tq == 0) TG[ti * LDT + j] = -taus[j] * s;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int q = 0; q < NQ; q++) {
+                    const int p = tq + 4 * q;
+                    if (p >= ti) TG[ti * LDT + p] = Tr[q];
                 }
             }
         }
+        PHASE_TS(t, 4);
 
         {
             const int l = opaque_lane(), cl = l & 15;
@@ -363,7 +390,9 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                         if (row < trows && col < k) Yt[row * ldy + col] = x[rb][ct][v];
                     }
         }
+        PHASE_TS(t, 5);
         __syncthreads();  // T complete, Y rows visible to the whole workgroup
+        PHASE_TS(t, 6);
         {
             const int64_t ti = (int64_t)c * L.maxtiles + t;
             double* Tg = L.Tt + ti * KP * KP;
@@ -379,13 +408,20 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         //   plain tile 0:     N^T  = V_0[0:k] - L_0 T^T (Y^T V),  L_0 = Y_0[0:k, 0:k]
         if (HASV && k0 > 0) {
             const int l = opaque_lane(), g = l >> 4, cl = l & 15;
+            // S^T = N^T + Y^T V (structured) or Y^T V (plain); the N^T loads are
+            // issued first so that they overlap the product loop
             d4 sacc[CT][NJW];
 #pragma unroll
             for (int mi = 0; mi < CT; mi++)
 #pragma unroll
-                for (int q = 0; q < NJW; q++) sacc[mi][q] = d4zero();
+                for (int q = 0; q < NJW; q++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
+                        sacc[mi][q][v] = (!plain && cc < K0P) ? NT[r * K0P + cc] : 0.0;
+                    }
             // B^T = Y^T V over the tile rows (4 rows per K-step)
-            constexpr int US = 2;
+            constexpr int US = 4;  // K-steps per batch of loads (the tile registers are free here)
             for (int s0 = 0; s0 < TB / 4; s0 += US) {
                 double ya[US][CT], vb[US][NJW];
 #pragma unroll
@@ -409,17 +445,6 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     for (int mi = 0; mi < CT; mi++)
 #pragma unroll
                         for (int q = 0; q < NJW; q++) sacc[mi][q] = mfma(ya[u][mi], vb[u][q], sacc[mi][q]);
-            }
-            if (!plain) {
-#pragma unroll
-                for (int mi = 0; mi < CT; mi++)
-#pragma unroll
-                    for (int q = 0; q < NJW; q++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
-                            if (cc < K0P) sacc[mi][q][v] += NT[r * K0P + cc];
-                        }
             }
             // D^T = T^T S^T, contracting over the rows of S^T (K-step (rb, v)
             // takes rows 16 rb + l/16 + 4 v, i.e. register v of block rb)
