@@ -601,6 +601,8 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
         d4 kk[NTKW];
 #pragma unroll
         for (int i = 0; i < NTKW; i++) kk[i] = d4zero();
+        // contraction index split as g * KSK + s: a lane reads KSK consecutive
+        // entries of one row of T_t (one 128-byte piece per lane group)
 #pragma unroll
         for (int s = 0; s < KSK; s++)
 #pragma unroll
@@ -608,8 +610,8 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
                 const int id = w + NW * i;
                 if (id < NTK) {
                     const int mi = id / CT, nj = id % CT;
-                    const double a = Tg[(16 * mi + cl) * KP + 4 * s + g];
-                    kk[i] = mfma(a, src[(4 * s + g) * LDT + 16 * nj + cl], kk[i]);
+                    const double a = Tg[(16 * mi + cl) * KP + g * KSK + s];
+                    kk[i] = mfma(a, src[(g * KSK + s) * LDT + 16 * nj + cl], kk[i]);
                 }
             }
         __syncthreads();
@@ -654,20 +656,31 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
                     for (int ct = 0; ct < CT; ct++)
                         acc[rb][ct] = mfma(a[s], Kp[(s * CT + ct) * 64 + l], acc[rb][ct]);
             }
-            if (PANEL == PANEL_F64 && HASV && k0 > 0) {
-                const double* vp = Vt + yr * ldv + g * KS0;
-                constexpr int HS = (KS0 > 16) ? 16 : KS0;
+        }
+        // + V N: K-steps outer so that each B-operand load of N serves every
+        // row block (N is read in operand order, see k_permute_b)
+        if (PANEL == PANEL_F64 && HASV && k0 > 0) {
+            constexpr int SC = 4;  // K-steps per batch of loads
+#pragma unroll 2
+            for (int s0 = 0; s0 < KS0; s0 += SC) {
+                double a[RB][SC], b[SC][CT];
 #pragma unroll
-                for (int s0 = 0; s0 < KS0; s0 += HS) {
-                    double a[HS];
+                for (int rb = 0; rb < RB; rb++) {
+                    const int yr = RPW * w + 16 * rb + cl;
+                    const double* vp = Vt + yr * ldv + g * KS0 + s0;
 #pragma unroll
-                    for (int s = 0; s < HS; s++) a[s] = (ok && g * KS0 + s0 + s < k0) ? vp[s0 + s] : 0.0;
-#pragma unroll
-                    for (int s = 0; s < HS; s++)
-#pragma unroll
-                        for (int ct = 0; ct < CT; ct++)
-                            acc[rb][ct] = mfma(a[s], Np[((s0 + s) * CT + ct) * 64 + l], acc[rb][ct]);
+                    for (int s = 0; s < SC; s++) a[rb][s] = (yr < trows && g * KS0 + s0 + s < k0) ? vp[s] : 0.0;
                 }
+#pragma unroll
+                for (int s = 0; s < SC; s++)
+#pragma unroll
+                    for (int ct = 0; ct < CT; ct++) b[s][ct] = Np[((s0 + s) * CT + ct) * 64 + l];
+#pragma unroll
+                for (int s = 0; s < SC; s++)
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                        for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
             }
         }
         if (PANEL != PANEL_F64 && HASV && k0 > 0)
