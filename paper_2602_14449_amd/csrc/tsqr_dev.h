@@ -122,15 +122,28 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
                 const double xv = xw[rb * 16 + g * 4 + v];
                 xs[rb][v] = (!PLAIN || tile_row<RPW>(w, rb, l, v) > j) ? xv : 0.0;
             }
+        {
+            // CT independent dot products, interleaved so that the FMA chains
+            // and the cross-lane reductions pipeline
+            double sc[CT];
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            double s = 0.0;
+            for (int ct = 0; ct < CT; ct++) sc[ct] = 0.0;
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) s += xs[rb][v] * x[rb][ct][v];
-            s = sum_groups(s);
-            if (g == 0) part[(pb * NW + w) * KP + 16 * ct + cl] = s;
+                for (int v = 0; v < 4; v++)
+#pragma unroll
+                    for (int ct = 0; ct < CT; ct++) sc[ct] += xs[rb][v] * x[rb][ct][v];
+            dpair p16[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) p16[ct] = pair16(sc[ct]);
+            dpair p32[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) p32[ct] = pair32(p16[ct].even + p16[ct].odd);
+            if (g == 0) {
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) part[(pb * NW + w) * KP + 16 * ct + cl] = p32[ct].even + p32[ct].odd;
+            }
         }
         if (PLAIN && w == j / RPW) {
             // publish the pivot row (row j of the tile)
