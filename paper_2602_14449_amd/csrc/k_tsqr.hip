@@ -14,6 +14,18 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
     form_chunk<KP, K0P, PANEL, 0>(L, blockIdx.x);
 }
 
+template <int KP>
+__global__ __launch_bounds__(NW * 64, 2) void k_tsqr_kchain(TsqrLevel L) {
+    kchain_chunk<KP>(L, blockIdx.x);
+}
+
+// one workgroup per tile slot (chunk-major, so that consecutive workgroups
+// stream consecutive rows)
+template <int KP, int K0P, int PANEL>
+__global__ __launch_bounds__(NW * 64, 2) void k_tsqr_rows(TsqrLevel L) {
+    rows_tile<KP, K0P, PANEL>(L, blockIdx.x / L.maxtiles, blockIdx.x % L.maxtiles);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int KP, int K0P, int PANEL>
@@ -41,6 +53,28 @@ static hipError_t form_t(const TsqrLevel& L, hipStream_t st) {
         attr = true;
     }
     hipLaunchKernelGGL((k_tsqr_form<KP, K0P, PANEL>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
+    return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t kchain_t(const TsqrLevel& L, hipStream_t st) {
+    const size_t shm = KchainLds<KP>::total * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_kchain<KP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_tsqr_kchain<KP>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
+    return hipGetLastError();
+}
+
+template <int KP, int K0P, int PANEL>
+static hipError_t rows_t(const TsqrLevel& L, hipStream_t st) {
+    const int64_t nb = (int64_t)L.nchunk * L.maxtiles;
+    if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tsqr_rows<KP, K0P, PANEL>), dim3((unsigned)nb), dim3(NW * 64), 0, st, L);
     return hipGetLastError();
 }
 
@@ -98,10 +132,30 @@ hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipS
     TSQR_DISPATCH(leaf_t)
 }
 
-hipError_t launch_tsqr_form(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st) {
-    if (panel == PANEL_F32X2) TSQR_DISPATCH_LOWP(form_t, PANEL_F32X2)
-    if (panel == PANEL_BF16) TSQR_DISPATCH_LOWP(form_t, PANEL_BF16)
-    TSQR_DISPATCH(form_t)
+hipError_t launch_tsqr_form(int kp, const TsqrLevel& L, hipStream_t st) {
+    switch (kp) {
+        case 16: return form_t<16, 0, 0>(L, st);
+        case 32: return form_t<32, 0, 0>(L, st);
+        case 64: return form_t<64, 0, 0>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tsqr_kchain(int kp, const TsqrLevel& L, hipStream_t st) {
+    if (L.Cfin == nullptr) return hipErrorInvalidValue;
+    switch (kp) {
+        case 16: return kchain_t<16>(L, st);
+        case 32: return kchain_t<32>(L, st);
+        case 64: return kchain_t<64>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tsqr_rows(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st) {
+    if (L.Cfin == nullptr) return hipErrorInvalidValue;
+    if (panel == PANEL_F32X2) TSQR_DISPATCH_LOWP(rows_t, PANEL_F32X2)
+    if (panel == PANEL_BF16) TSQR_DISPATCH_LOWP(rows_t, PANEL_BF16)
+    TSQR_DISPATCH(rows_t)
 }
 
 }  // namespace tho

@@ -165,6 +165,14 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
     if (rc) return rc;
 
     if (k0 > 0) {
+        // the k x k recurrence of the level-0 formation needs neither G nor N:
+        // it runs on the side stream while they are computed
+        Fork& f = fork_for_thread();
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        rc = tsqr_kchain0(P.ts, Ls, f.side);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(f.ev1, f.side));
         // formation of Q: G = W^T [0; Q_] = -sum_c N_c G_c ;  N = T^{-1} G
         PROF("chunk_prod", st, launch_chunk_prod(Ls[0].nchunk, K0P, KP, ik, P.Nc, Ls[0].Gin, Ls[0].ldg, Ls[0].gstride,
                                  P.prod, st));
@@ -179,6 +187,8 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
                                  st));
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 0, P.Nglob, KP, 0, 1.0, Q, ldq, Q, ldq,
                                  st));
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
+        return tsqr_rows0(P.ts, Ls, K0P, st, panel);
     }
     return tsqr_form0(P.ts, Ls, K0P, st, panel);
 }

@@ -135,6 +135,7 @@ void tsqr_plan(int64_t m0, int k, Carve& cv, TsqrPlan& T) {
     const size_t kk = (size_t)T.KP * T.KP;
     T.Rtop = cv.take(kk);
     T.G0 = cv.take(kk);
+    T.Cfin = cv.take((size_t)T.lv[0].nchunk * kk);
     const size_t nl = T.lv.size();
     T.tau.assign(nl, nullptr);
     T.Tt.assign(nl, nullptr);
@@ -170,6 +171,7 @@ std::vector<TsqrLevel> tsqr_levels(const TsqrPlan& T, const double* X, int64_t l
         }
         L.tau = T.tau[l];
         L.Tt = T.Tt[l];
+        L.Cfin = (l == 0) ? T.Cfin : nullptr;
         L.Rnext = (l + 1 < nl) ? T.stack[l + 1] : T.Rtop;
         L.ldrn = T.KP;
         if (l + 1 < nl) {
@@ -193,13 +195,24 @@ int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* 
              launch_tsqr_leaf(T.KP, l == 0 ? k0p : 0, l == 0 ? panel : 0, Ls[l], st));
     // R with nonnegative diagonal; the top-level Q starts from the sign matrix
     PROF("finish_r", st, launch_finish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
-    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(T.KP, 0, 0, Ls[l], st));
+    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(T.KP, Ls[l], st));
+    return 0;
+}
+
+int tsqr_kchain0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, hipStream_t st) {
+    PROF("kchain_l0", st, launch_tsqr_kchain(T.KP, Ls[0], st));
+    return 0;
+}
+
+int tsqr_rows0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel) {
+    PROF("form_l0", st, launch_tsqr_rows(T.KP, k0p, panel, Ls[0], st));
     return 0;
 }
 
 int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel) {
-    PROF("form_l0", st, launch_tsqr_form(T.KP, k0p, panel, Ls[0], st));
-    return 0;
+    int rc = tsqr_kchain0(T, Ls, st);
+    if (rc) return rc;
+    return tsqr_rows0(T, Ls, k0p, st, panel);
 }
 
 // about four workgroups per compute unit, >= 64 rows each

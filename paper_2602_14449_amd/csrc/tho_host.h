@@ -94,6 +94,7 @@ struct TsqrPlan {
     int k = 0, KP = 16;
     std::vector<LevelPlan> lv;
     double *Rtop = nullptr, *G0 = nullptr;
+    double* Cfin = nullptr;  // level 0: per chunk KP x KP (two-pass formation)
     std::vector<double*> tau, Tt, stack;  // stack[l] = input matrix of level l (l >= 1)
 };
 
@@ -109,7 +110,11 @@ std::vector<TsqrLevel> tsqr_levels(const TsqrPlan& T, const double* X, int64_t l
 // (0: none); panel selects the arithmetic of level 0's V products.
 int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* R, int64_t ldr, hipStream_t st,
                 int panel = 0);
-// Formation of level 0 (rows of Q into Ls[0].Y).
+// Formation of level 0 (rows of Q into Ls[0].Y): tsqr_kchain0 (needs the
+// formed level 1 only; consumes the level-0 T factors) then tsqr_rows0
+// (needs Ls[0].Nglob / Nlp when k0p > 0).  tsqr_form0 runs both in order.
+int tsqr_kchain0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, hipStream_t st);
+int tsqr_rows0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel = 0);
 int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream_t st, int panel = 0);
 
 // Split-n reduction out = X^T Y over nrows rows (X: p <= 128 columns, Y:

@@ -47,6 +47,9 @@ struct TsqrLevel {
     const double* Gin;
     int64_t ldg;
     int64_t gstride;
+    // two-pass formation of level 0: per chunk KP x KP, the block C that
+    // reaches the chunk's first tile (row-major, zero outside k x k)
+    double* Cfin;
 };
 
 hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
@@ -168,7 +171,13 @@ hipError_t launch_pack_b(int p, int q, const double* src, int64_t lds, int trans
 // kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term); panel
 // 0 = FP64, 1 = FP32 hi + lo, 2 = BF16 for the V products (k0p > 0 only).
 hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
-hipError_t launch_tsqr_form(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
+// Formation of a level above 0 (no V term), one workgroup per chunk.
+hipError_t launch_tsqr_form(int kp, const TsqrLevel& L, hipStream_t st);
+// Two-pass formation of level 0: the per-chunk recurrence of the k x k
+// blocks (overwrites each T_t with -K_t and fills Cfin), then every tile's
+// rows of Q independently.
+hipError_t launch_tsqr_kchain(int kp, const TsqrLevel& L, hipStream_t st);
+hipError_t launch_tsqr_rows(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
 
 // Reduced-precision panels (k_lowp.hip): C = X^T Y with FP32 hi + lo or
 // BF16 products (same layout as launch_xty_partial), and the packing of a

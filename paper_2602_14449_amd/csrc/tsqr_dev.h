@@ -10,7 +10,9 @@
 // place of the rows of Q they will become) and its compact-WY factor T_t
 // (H_t = I - U_t T_t U_t^T), so Q can be formed later without refactoring.
 // The chunk R factors are stacked into the matrix of the next level, which is
-// reduced the same way until one chunk remains.
+// reduced the same way until one chunk remains.  Q is formed top-down: the
+// upper levels chunk by chunk (form_chunk), level 0 in two passes (the k x k
+// recurrence per chunk, then every tile on its own; see kchain_chunk).
 //
 // Level 0 (the bottom n - k0 rows of A) is fused with the generalized
 // Householder step of Algorithm 1: the tile loaded from A is updated to
@@ -709,6 +711,263 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
                 }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Formation of level 0 in two passes.  The only sequential dependence of the
+// flat-tree formation is through the k x k block C that each tile hands to the
+// one above it (top-down: K_t = T_t C, C <- C - K_t for a structured tile;
+// K_0 = T_0 L_0^T C for the plain tile 0, whose top k rows also receive C).
+// kchain_chunk walks that recurrence for one chunk and overwrites every T_t
+// in place with -K_t (in B-operand order, see k_permute_b) and stores the
+// final C; rows_tile then forms the Q rows of any tile on its own,
+//   Q_t = [C; 0] (tile 0 only) - Y_t K_t + V_t N,
+// with no barrier and no shared memory, so that the streaming MFMA work runs
+// at full occupancy over every tile of every chunk at once.
+
+template <int KP>
+struct KchainLds {
+    static constexpr int LDT = KP + 1;
+    static constexpr int total = 2 * KP * LDT;
+};
+
+template <int KP>
+__device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
+    constexpr int TB = Geo<KP>::TB;
+    constexpr int CT = KP / 16;
+    constexpr int LDT = KP + 1;
+    constexpr int KSK = KP / 4;
+    constexpr int NTK = CT * CT;
+    constexpr int NTKW = (NTK + NW - 1) / NW;
+    constexpr int PT = KP * KP / (NW * 64);  // entries of T_t per thread
+    static_assert(PT * NW * 64 == KP * KP, "one T_t per workgroup pass");
+
+    extern __shared__ double sm[];
+    double* Cm = sm;             // KP x LDT: the running C
+    double* Tb = Cm + KP * LDT;  // KP x LDT: T_t (structured tiles), L_0^T C (plain tile)
+
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int k = L.k;
+    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
+    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
+    const int ntiles = (int)((cr1 - cr0 + TB - 1) / TB);
+    {
+        const double* G = L.Gin + (int64_t)c * L.gstride * L.ldg;
+        for (int e = tid; e < KP * KP; e += blockDim.x) {
+            const int i = e / KP, jj = e % KP;
+            Cm[i * LDT + jj] = (i < k && jj < k) ? G[(int64_t)i * L.ldg + jj] : 0.0;
+        }
+    }
+    // T_t of the next structured tile is fetched one step ahead (PT values
+    // per thread) and staged into Tb once the current step has read it
+    double tp[PT];
+    auto fetch = [&](int t) {
+        const double* Tg = L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP;
+#pragma unroll
+        for (int q = 0; q < PT; q++) tp[q] = Tg[tid + q * NW * 64];
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < PT; q++) {
+            const int e = tid + q * NW * 64;
+            Tb[(e / KP) * LDT + e % KP] = tp[q];
+        }
+    };
+    if (ntiles > 1) {
+        fetch(ntiles - 1);
+        stage();
+    }
+    __syncthreads();
+    const int l = lane_id(), g = l >> 4, cl = l & 15;
+
+    for (int t = ntiles - 1; t >= 0; t--) {
+        const bool plain = (t == 0);
+        double* Kg = L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP;
+        d4 kk[NTKW];
+#pragma unroll
+        for (int i = 0; i < NTKW; i++) kk[i] = d4zero();
+        if (!plain) {
+            if (t > 1) fetch(t - 1);
+            // K = T_t C; contraction index g * KSK + s
+#pragma unroll 4
+            for (int s = 0; s < KSK; s++)
+#pragma unroll
+                for (int i = 0; i < NTKW; i++) {
+                    const int id = w + NW * i;
+                    if (id < NTK) {
+                        const int mi = id / CT, nj = id % CT;
+                        kk[i] = mfma(Tb[(16 * mi + cl) * LDT + g * KSK + s], Cm[(g * KSK + s) * LDT + 16 * nj + cl],
+                                     kk[i]);
+                    }
+                }
+        } else {
+            // E = L_0^T C with L_0 = Y_0[0:k, 0:k] (unit lower triangular) into Tb
+            const double* Y0 = L.Y + cr0 * L.ldy;
+            const int ldy = (int)L.ldy;
+            d4 e[NTKW];
+#pragma unroll
+            for (int i = 0; i < NTKW; i++) e[i] = d4zero();
+#pragma unroll 4
+            for (int s = 0; s < KSK; s++)
+#pragma unroll
+                for (int i = 0; i < NTKW; i++) {
+                    const int id = w + NW * i;
+                    if (id < NTK) {
+                        const int mi = id / CT, nj = id % CT;
+                        const int yr = 4 * s + g, yc = 16 * mi + cl;
+                        const double a = (yr < k && yc < k) ? Y0[yr * ldy + yc] : 0.0;
+                        e[i] = mfma(a, Cm[(4 * s + g) * LDT + 16 * nj + cl], e[i]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < NTKW; i++) {
+                const int id = w + NW * i;
+                if (id < NTK) {
+                    const int mi = id / CT, nj = id % CT;
+#pragma unroll
+                    for (int v = 0; v < 4; v++) Tb[(16 * mi + drow(l, v)) * LDT + 16 * nj + cl] = e[i][v];
+                }
+            }
+            __syncthreads();
+            // K = T_0 E (T_0 straight from its slot)
+#pragma unroll 4
+            for (int s = 0; s < KSK; s++)
+#pragma unroll
+                for (int i = 0; i < NTKW; i++) {
+                    const int id = w + NW * i;
+                    if (id < NTK) {
+                        const int mi = id / CT, nj = id % CT;
+                        kk[i] = mfma(Kg[(16 * mi + cl) * KP + g * KSK + s], Tb[(g * KSK + s) * LDT + 16 * nj + cl],
+                                     kk[i]);
+                    }
+                }
+        }
+        __syncthreads();  // every read of C, Tb and T_t is done
+#pragma unroll
+        for (int i = 0; i < NTKW; i++) {
+            const int id = w + NW * i;
+            if (id < NTK) {
+                const int mi = id / CT, nj = id % CT;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int r = 16 * mi + drow(l, v), cc = 16 * nj + cl;
+                    Kg[((r % KSK) * CT + nj) * 64 + 16 * (r / KSK) + cl] = -kk[i][v];
+                    if (!plain) Cm[r * LDT + cc] -= kk[i][v];
+                }
+            }
+        }
+        if (!plain && t > 1) stage();
+        __syncthreads();
+    }
+    // C as the plain tile 0 sees it (zero outside the k x k block)
+    double* Cf = L.Cfin + (int64_t)c * KP * KP;
+    for (int e = tid; e < KP * KP; e += blockDim.x) Cf[e] = Cm[(e / KP) * LDT + e % KP];
+}
+
+// acc[rb][ct] += X[rows, :] B over the rows RPW w + 16 rb + (0..15) of a
+// tile: X row-major (ld ldx), contraction index g * KS + s (a lane reads KS
+// consecutive entries of its row; columns >= kmax read as zero), B a
+// (4 KS) x (16 CT) matrix in B-operand order.  K-steps are taken eight at a
+// time, each B load serving every row block.
+template <int RB, int CT, int KS>
+__device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
+                                          int trows, int kmax, const double* __restrict__ B, int l) {
+    constexpr int SC = (KS < 8) ? KS : 8;
+    const int g = l >> 4, cl = l & 15;
+#pragma unroll 2
+    for (int s0 = 0; s0 < KS; s0 += SC) {
+        double a[RB][SC], b[SC][CT];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const int xr = row0 + 16 * rb + cl;
+            const double* xp = X + xr * ldx + g * KS + s0;
+#pragma unroll
+            for (int s = 0; s < SC; s++) a[rb][s] = (xr < trows && g * KS + s0 + s < kmax) ? xp[s] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
+    }
+}
+
+template <int KP, int K0P, int PANEL>
+__device__ __forceinline__ void rows_tile(const TsqrLevel& L, const int c, const int t) {
+    constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
+    constexpr int CT = KP / 16;
+    constexpr int KSK = KP / 4;
+    constexpr bool HASV = K0P > 0;
+    constexpr int KS0 = (K0P > 0) ? K0P / 4 : 1;
+
+    const int w = threadIdx.x >> 6;
+    const int k = L.k;
+    const int k0 = HASV ? L.k0 : 0;
+    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
+    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
+    const int64_t r0 = cr0 + (int64_t)t * TB;
+    if (r0 >= cr1) return;  // slot beyond this chunk's tiles (uniform)
+    const int trows = (int)((cr1 - r0 < TB) ? (cr1 - r0) : TB);
+    const double* __restrict__ Kg = L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP;  // -K_t
+    double* __restrict__ Yt = L.Y + r0 * L.ldy;
+    const double* __restrict__ Vt = HASV ? L.V + r0 * L.ldv : nullptr;
+    const int ldy = (int)L.ldy, ldv = (int)L.ldv;
+    const int l = lane_id(), g = l >> 4, cl = l & 15;
+
+    d4 acc[RB][CT];
+    if (t == 0) {
+        const double* Cf = L.Cfin + (int64_t)c * KP * KP;
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
+                    acc[rb][ct][v] = (row < KP) ? Cf[row * KP + col] : 0.0;
+                }
+    } else {
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) acc[rb][ct] = d4zero();
+    }
+    // - Y_t K_t: all KSK K-steps at once (the loads of Y and of K_t are
+    // issued together, deepest memory-level parallelism)
+    {
+        const int g = l >> 4, cl = l & 15;
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const int yr = RPW * w + 16 * rb + cl;
+            const double* yp = Yt + yr * ldy + g * KSK;
+            double a[KSK];
+#pragma unroll
+            for (int s = 0; s < KSK; s++) a[s] = (yr < trows && g * KSK + s < k) ? yp[s] : 0.0;
+#pragma unroll
+            for (int s = 0; s < KSK; s++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[s], Kg[(s * CT + ct) * 64 + l], acc[rb][ct]);
+        }
+    }
+    // + V_t N (N in B-operand order, see k_permute_b)
+    if (PANEL == PANEL_F64 && HASV && k0 > 0) rows_prod<RB, CT, KS0>(acc, Vt, ldv, RPW * w, trows, k0, L.Nglob, l);
+    if (PANEL != PANEL_F64 && HASV && k0 > 0)
+        vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(acc, Vt, ldv, RPW * w, trows, k0, L.Nlp, l);
+    // each wavefront reads and writes only its own rows: no barrier
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = tile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
+                if (row < trows && col < k) Yt[row * ldy + col] = acc[rb][ct][v];
+            }
 }
 
 }  // namespace tho
