@@ -60,6 +60,49 @@ __device__ __forceinline__ dpair pair32(double x) {
     return {dmake(lo[0], hi[0]), dmake(lo[1], hi[1])};
 }
 
+// v_permlane16_swap / v_permlane32_swap on two different doubles (no
+// copies): swap16 exchanges the odd 16-lane rows of a with the even rows of
+// b; swap32 exchanges the upper 32-lane half of a with the lower half of b.
+__device__ __forceinline__ void swap16(double& a, double& b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(dlo(a), dlo(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(dhi(a), dhi(b), false, false);
+    a = dmake(lo[0], hi[0]);
+    b = dmake(lo[1], hi[1]);
+}
+__device__ __forceinline__ void swap32(double& a, double& b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(dlo(a), dlo(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(dhi(a), dhi(b), false, false);
+    a = dmake(lo[0], hi[0]);
+    b = dmake(lo[1], hi[1]);
+}
+
+// Column sums of CT per-lane partial values s[ct] (lane l holding a partial
+// for column 16 ct + l % 16): returns, in lane l < 16 CT, the sum over the
+// four 16-lane groups for column l.  Two values share every swap, so no
+// lane moves are spent on copies (CT = 4: four permlane16 and two
+// permlane32 swaps, three adds).
+template <int CT>
+__device__ __forceinline__ double col_sums(double (&s)[CT]) {
+    if constexpr (CT == 4) {
+        double a = s[0], b = s[1], c = s[2], d = s[3];
+        swap16(a, b);  // a: rows (0+1 of s0, 0+1 of s1, 2+3 of s0, 2+3 of s1) after a + b
+        swap16(c, d);
+        double p = a + b, q = c + d;
+        swap32(p, q);  // p + q: row r holds the total of s[r]
+        return p + q;
+    } else if constexpr (CT == 2) {
+        double a = s[0], b = s[1];
+        swap16(a, b);
+        double p = a + b, q = p;
+        swap32(p, q);  // rows 0 and 1 hold the totals of s[0] and s[1]
+        return p + q;
+    } else {
+        const dpair e = pair16(s[0]);
+        const dpair f = pair32(e.even + e.odd);
+        return f.even + f.odd;
+    }
+}
+
 // Sum across the four 16-lane groups of a wavefront (lanes l, l^16, l^32,
 // l^48 end up with the same value, bitwise).
 __device__ __forceinline__ double sum_groups(double x) {

@@ -104,13 +104,18 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
     double* xw = xcol + RPW * w;  // this wavefront's pivot column, lane-group order
     for (int j = 0; j < k; j++) {
         const int pb = j & 1, ctj = j >> 4, clj = j & 15;
+        // (ct == ctj is uniform: the empty asm keeps it a scalar branch, so
+        // the three other column blocks cost nothing)
 #pragma unroll
         for (int ct = 0; ct < CT; ct++) {
-            if (ct == ctj && cl == clj) {
+            if (ct == ctj) {
+                asm volatile("");
+                if (cl == clj) {
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++)
+                    for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                    for (int v = 0; v < 4; v++) xw[rb * 16 + g * 4 + v] = x[rb][ct][v];
+                        for (int v = 0; v < 4; v++) xw[rb * 16 + g * 4 + v] = x[rb][ct][v];
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -136,16 +141,8 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
                 for (int v = 0; v < 4; v++)
 #pragma unroll
                     for (int ct = 0; ct < CT; ct++) sc[ct] += xs[rb][v] * x[rb][ct][v];
-            dpair p16[CT];
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) p16[ct] = pair16(sc[ct]);
-            dpair p32[CT];
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) p32[ct] = pair32(p16[ct].even + p16[ct].odd);
-            if (g == 0) {
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++) part[(pb * NW + w) * KP + 16 * ct + cl] = p32[ct].even + p32[ct].odd;
-            }
+            const double tot = col_sums<CT>(sc);  // valid in lanes l < KP
+            if (l < KP) part[(pb * NW + w) * KP + l] = tot;
         }
         if (PLAIN && w == j / RPW) {
             // publish the pivot row (row j of the tile)
@@ -212,7 +209,9 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
         // column j becomes the Householder vector (and beta on the pivot)
 #pragma unroll
         for (int ct = 0; ct < CT; ct++) {
-            if (ct == ctj && cl == clj) {
+            if (ct != ctj) continue;
+            asm volatile("");
+            if (cl == clj) {
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++)
 #pragma unroll
