@@ -191,20 +191,29 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
         double wv[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ct++) wv[ct] = wv4[ct];
-        double u[RB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int v = 0; v < 4; v++)
-                u[rb][v] = (PLAIN && tile_row<RPW>(w, rb, l, v) == j) ? 1.0 : xs[rb][v] * scale;
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            const int col = 16 * ct + cl;
-            const double coef = (col > j && col < k) ? tau * wv[ct] : 0.0;
+        // rank-1 update of the columns right of j.  Blocks left of the pivot
+        // block hold Householder vectors only and are skipped (uniform
+        // branch); padding columns (>= k) stay zero by themselves, as their
+        // pivot-row entries and dot products are zero.
+        double u[RB][4];  // reflector on my rows; structured: scale * xs
+        if (PLAIN) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) x[rb][ct][v] -= coef * u[rb][v];
+                for (int v = 0; v < 4; v++)
+                    u[rb][v] = (tile_row<RPW>(w, rb, l, v) == j) ? 1.0 : xs[rb][v] * scale;
+        }
+        const double ts = PLAIN ? tau : tau * scale;
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+            if (ct < ctj) continue;
+            asm volatile("");
+            const double cw = ts * wv[ct];
+            const double coef = (ct > ctj || cl > clj) ? cw : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) x[rb][ct][v] -= coef * (PLAIN ? u[rb][v] : xs[rb][v]);
         }
         // column j becomes the Householder vector (and beta on the pivot)
 #pragma unroll
@@ -264,6 +273,10 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
     // wavefront w owns its 16-column blocks nj = w, w + NW, ... (all rows) and
     // is the only one to read or write them.
     double* NT = (HASV && k0 > 0) ? L.Nc + (int64_t)c * KP * K0P : nullptr;
+
+    // TG starts at zero, so that it only ever holds finite values (the T
+    // sweep multiplies whole rows of it by zeros instead of masking)
+    for (int e = tid; e < KP * LDT; e += blockDim.x) TG[e] = 0.0;
 
     for (int t = 0; t < ntiles; t++) {
         if (t > 0) __syncthreads();  // readers of TG from the last tile are done
@@ -338,9 +351,10 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         // entries p = lane + 4 q in registers; step j reads row j of the Gram
         // (Gm(j,p) = u_p^T u_j, strict lower triangle of TG; the same
         // addresses for every row, so mostly broadcasts) and reduces over the
-        // four lanes with quad shuffles.  Entries p >= j of a row are still
-        // zero at step j, so no masking is needed.  T goes to the upper
-        // triangle of TG (disjoint from Gm).
+        // four lanes with quad shuffles.  Entries p >= j of a row ti < j are
+        // still zero at step j and TG holds only finite values, so the loads
+        // need no mask (rows ti >= j compute values they never keep).  T goes
+        // to the upper triangle of TG (disjoint from Gm).
         {
             constexpr int NQ = KP / 4;
             const int tq = tid & 3, ti = tid >> 2;  // 64 rows x 4 lanes
@@ -348,14 +362,13 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) Tr[q] = (tq + 4 * q == ti && ti < k) ? taus[ti] : 0.0;
             for (int j = 1; j < k; j++) {
-                // all loads are in bounds (j, p < KP): issue them unconditionally
-                // and mask the values, four independent partial sums
+                // all loads are in bounds (j, p < KP); four independent partial sums
                 double g[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; q++) g[q] = TG[j * LDT + tq + 4 * q];
                 double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int q = 0; q < NQ; q++) s4[q & 3] += Tr[q] * ((tq + 4 * q < j) ? g[q] : 0.0);
+                for (int q = 0; q < NQ; q++) s4[q & 3] += Tr[q] * g[q];
                 double sr = (s4[0] + s4[1]) + (s4[2] + s4[3]);
                 sr = sum_quad(sr);
                 if (j > ti && tq == (j & 3)) {
