@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--n", type=int, default=None)
     p.add_argument("--k0", type=int, default=None)
     p.add_argument("--k", type=int, default=None)
-    p.add_argument("--cpu-rows", type=int, default=1 << 20)
+    p.add_argument("--cpu-rows", type=int, default=1 << 22)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--no-compare", action="store_true", help="skip the comparison methods (graded only)")
