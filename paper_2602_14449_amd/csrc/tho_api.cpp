@@ -165,6 +165,11 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
     if (rc) return rc;
 
     if (k0 > 0) {
+        // formation of Q: G = W^T [0; Q_] = -sum_c N_c G_c ;  N = T^{-1} G.
+        // The per-chunk products go first (short, and they need more shared
+        // memory than is left beside the chain below).
+        PROF("chunk_prod", st, launch_chunk_prod(Ls[0].nchunk, K0P, KP, ik, P.Nc, Ls[0].Gin, Ls[0].ldg, Ls[0].gstride,
+                                 P.prod, st));
         // the k x k recurrence of the level-0 formation needs neither G nor N:
         // it runs on the side stream while they are computed
         Fork& f = fork_for_thread();
@@ -173,9 +178,6 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
         rc = tsqr_kchain0(P.ts, Ls, f.side);
         if (rc) return rc;
         HIPCHK(hipEventRecord(f.ev1, f.side));
-        // formation of Q: G = W^T [0; Q_] = -sum_c N_c G_c ;  N = T^{-1} G
-        PROF("chunk_prod", st, launch_chunk_prod(Ls[0].nchunk, K0P, KP, ik, P.Nc, Ls[0].Gin, Ls[0].ldg, Ls[0].gstride,
-                                 P.prod, st));
         PROF("reduce_parts", st, launch_reduce_parts(Ls[0].nchunk, (int64_t)K0P * KP, P.prod, P.Mbuf, st));
         PROF("small_gemm", st, launch_small_gemm(K0P, KP, 0, 0.0, P.Mbuf, KP, 0, P.Mbuf, KP, 0, -1.0, P.Mbuf, KP,
                                  P.Nglob, KP, st));

@@ -800,18 +800,18 @@ __device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
         for (int i = 0; i < NTKW; i++) kk[i] = d4zero();
         if (!plain) {
             if (t > 1) fetch(t - 1);
-            // K = T_t C; contraction index g * KSK + s
-#pragma unroll 4
-            for (int s = 0; s < KSK; s++)
+            // K = T_t C, contraction index 4 s + g; T_t is upper triangular, so
+            // row block mi starts at K-step 4 mi
 #pragma unroll
-                for (int i = 0; i < NTKW; i++) {
-                    const int id = w + NW * i;
-                    if (id < NTK) {
-                        const int mi = id / CT, nj = id % CT;
-                        kk[i] = mfma(Tb[(16 * mi + cl) * LDT + g * KSK + s], Cm[(g * KSK + s) * LDT + 16 * nj + cl],
-                                     kk[i]);
-                    }
+            for (int i = 0; i < NTKW; i++) {
+                const int id = w + NW * i;
+                if (id < NTK) {
+                    const int mi = id / CT, nj = id % CT;
+#pragma unroll 4
+                    for (int s = 4 * mi; s < KSK; s++)
+                        kk[i] = mfma(Tb[(16 * mi + cl) * LDT + 4 * s + g], Cm[(4 * s + g) * LDT + 16 * nj + cl], kk[i]);
                 }
+            }
         } else {
             // E = L_0^T C with L_0 = Y_0[0:k, 0:k] (unit lower triangular) into Tb
             const double* Y0 = L.Y + cr0 * L.ldy;
