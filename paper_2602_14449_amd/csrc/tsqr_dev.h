@@ -487,6 +487,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     const int p = 16 * rb + drow(l, v);
 #pragma unroll
                     for (int mi = 0; mi < CT; mi++) {
+                        if (rb > mi) continue;  // T^T is lower triangular
                         const int m = 16 * mi + cl;
                         const double a = (p <= m && m < k) ? TG[p * LDT + m] : 0.0;  // T^T(m, p)
 #pragma unroll
@@ -517,6 +518,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                         const int p = 16 * rb + drow(l, v);
 #pragma unroll
                         for (int mi = 0; mi < CT; mi++) {
+                            if (rb > mi) continue;  // L_0 is lower triangular
                             const int m = 16 * mi + cl;
                             const double a = (m < k && p < k) ? Yt[m * ldy + p] : 0.0;  // L_0(m, p)
 #pragma unroll
