@@ -242,6 +242,106 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
     return beta_prev;
 }
 
+// T factor of the tile in TG (see leaf_chunk).  Diagonal 16 x 16 blocks by
+// the column recurrence (four lanes per row, entries p = 16 b + lane + 4 q in
+// registers, quad reductions), then merges on MFMA.  TG holds only finite
+// values (it is cleared once per chunk), so no load needs a mask.  Ends
+// before a workgroup barrier of the caller.
+template <int KP>
+__device__ __forceinline__ void tile_t_factor(double* TG, const double* taus, int k, int w) {
+    constexpr int CT = KP / 16;
+    constexpr int LDT = KP + 1;
+    // thread index the compiler cannot hoist: addresses derived from it are
+    // recomputed here instead of being kept live across the tile loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (w < CT) {
+        const int tq = tid & 3, ti = tid >> 2;  // row ti = 16 w + (lane / 4) of block w
+        const int p0 = 16 * w + tq;             // entries p = p0 + 4 q
+        double Tr[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) Tr[q] = (p0 + 4 * q == ti && ti < k) ? taus[ti] : 0.0;
+        const int jend = (16 * w + 16 < k) ? 16 * w + 16 : k;
+        for (int j = 16 * w + 1; j < jend; j++) {
+            double sr = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) sr += Tr[q] * TG[j * LDT + p0 + 4 * q];
+            sr = sum_quad(sr);
+            const int qj = (j - 16 * w) >> 2;
+            const double v = -taus[j] * sr;
+            const bool mine = j > ti && tq == (j & 3);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q == qj && mine) Tr[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int p = p0 + 4 * q;
+            if (p >= ti) TG[ti * LDT + p] = Tr[q];
+        }
+    }
+    if constexpr (CT >= 2) {
+        const int l = tid & 63, g = l >> 4, cl = l & 15;
+        __syncthreads();
+        // pairs of 16: blocks (a, b) = (2 w, 2 w + 1)
+        if (w < CT / 2) {
+            const int a = 2 * w, b = 2 * w + 1;
+            d4 x = d4zero(), y = d4zero();
+#pragma unroll
+            for (int s = 0; s < 4; s++) {  // X = G_ab T_b, K index 4 s + g
+                const int kk = 4 * s + g;
+                const double ga = TG[(16 * b + kk) * LDT + 16 * a + cl];
+                const double tb = (kk <= cl) ? TG[(16 * b + kk) * LDT + 16 * b + cl] : 0.0;
+                x = mfma(ga, tb, x);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; s++) {  // Y = T_a X; X in D layout is the B operand of K-step s = v
+                const int kk = 4 * s + g;
+                const double ta = (cl <= kk) ? TG[(16 * a + cl) * LDT + 16 * a + kk] : 0.0;
+                y = mfma(ta, x[s], y);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; v++) TG[(16 * a + g + 4 * v) * LDT + 16 * b + cl] = -y[v];
+        }
+        if constexpr (CT == 4) {
+            // pairs of 32: rows {0,1} x columns {2,3}; wavefront w owns block (ia, jb)
+            const int ia = w >> 1, jb = 2 + (w & 1);
+            __syncthreads();
+            d4 x = d4zero();
+#pragma unroll
+            for (int kb = 2; kb < 4; kb++) {
+                if (kb > jb) continue;  // T_BB is upper triangular
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const int kk = 4 * s + g;
+                    const double ga = TG[(16 * kb + kk) * LDT + 16 * ia + cl];
+                    const double tb =
+                        (kb < jb || kk <= cl) ? TG[(16 * kb + kk) * LDT + 16 * jb + cl] : 0.0;
+                    x = mfma(ga, tb, x);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = x[v];
+            __syncthreads();
+            d4 y = d4zero();
+#pragma unroll
+            for (int ka = 0; ka < 2; ka++) {
+                if (ka < ia) continue;  // T_AA is upper triangular
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const int kk = 4 * s + g;
+                    const double ta =
+                        (ka > ia || cl <= kk) ? TG[(16 * ia + cl) * LDT + 16 * ka + kk] : 0.0;
+                    y = mfma(ta, TG[(16 * ka + kk) * LDT + 16 * jb + cl], y);
+                }
+            }
+            __syncthreads();  // every X block has been read
+#pragma unroll
+            for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = -y[v];
+        }
+    }
+}
+
 }  // namespace
 
 template <int KP, int K0P, int PANEL, int RBO>
@@ -345,49 +445,8 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         // row k-1 of the slot has no trailing columns; only its diagonal changes
         if (!plain && w == 0 && k > 0 && (threadIdx.x & 63) == k - 1) slot[(k - 1) * LDT + (k - 1)] = beta_last;
         PHASE_TS(t, 2);
-        // compact-WY factor (H_0 ... H_{k-1} = I - U T U^T):
-        //   T(i,i) = tau_i,  T(i,j) = -tau_j sum_{i<=p<j} T(i,p) u_p^T u_j
-        // Rows of T are independent.  Four lanes own a row and keep its
-        // entries p = lane + 4 q in registers; step j reads row j of the Gram
-        // (Gm(j,p) = u_p^T u_j, strict lower triangle of TG; the same
-        // addresses for every row, so mostly broadcasts) and reduces over the
-        // four lanes with quad shuffles.  Entries p >= j of a row ti < j are
-        // still zero at step j and TG holds only finite values, so the loads
-        // need no mask (rows ti >= j compute values they never keep).  T goes
-        // to the upper triangle of TG (disjoint from Gm).
-        {
-            constexpr int NQ = KP / 4;
-            const int tq = tid & 3, ti = tid >> 2;  // 64 rows x 4 lanes
-            double Tr[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; q++) Tr[q] = (tq + 4 * q == ti && ti < k) ? taus[ti] : 0.0;
-            for (int j = 1; j < k; j++) {
-                // all loads are in bounds (j, p < KP); four independent partial sums
-                double g[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; q++) g[q] = TG[j * LDT + tq + 4 * q];
-                double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int q = 0; q < NQ; q++) s4[q & 3] += Tr[q] * g[q];
-                double sr = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                sr = sum_quad(sr);
-                if (j > ti && tq == (j & 3)) {
-                    const double v = -taus[j] * sr;
-#pragma unroll
-                    for (int q = 0; q < NQ; q++)
-                        if (q == (j >> 2)) Tr[q] = v;
-                }
-            }
-            if (ti < k) {
-#pragma unroll
-                for (int q = 0; q < NQ; q++) {
-                    const int p = tq + 4 * q;
-                    if (p >= ti) TG[ti * LDT + p] = Tr[q];
-                }
-            }
-        }
-        PHASE_TS(t, 4);
-
+        // tile outputs first (R -> slot, registers -> Y), so that the tile
+        // registers are free during the T factor
         {
             const int l = opaque_lane(), cl = l & 15;
             if (plain) {
@@ -418,6 +477,17 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     }
         }
         PHASE_TS(t, 5);
+        // compact-WY factor (H_0 ... H_{k-1} = I - U T U^T):
+        //   T(i,i) = tau_i,  T(i,j) = -tau_j sum_{i<=p<j} T(i,p) u_p^T u_j
+        // in 16 x 16 blocks.  Each diagonal block is the factor of its own 16
+        // reflectors (the recurrence above, wavefront b for block b); two
+        // adjacent factors merge as
+        //   [T_a  X; 0  T_b],  X = -T_a (U_a^T U_b) T_b,
+        // first in pairs of 16 columns, then in pairs of 32, on MFMA.  The
+        // Gram U^T U sits in the strict lower triangle of TG (G(p, j) at
+        // TG[j][p]); T goes to the upper triangle.
+        tile_t_factor<KP>(TG, taus, k, w);
+        PHASE_TS(t, 4);
         __syncthreads();  // T complete, Y rows visible to the whole workgroup
         PHASE_TS(t, 6);
         {
