@@ -145,47 +145,53 @@ __global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __
 // B (n x m):
 //   trans == 0:  L X = B   (forward substitution)
 //   trans == 1:  L^T X = B (backward substitution; L^T is upper)
-// One 64-lane workgroup per column of B (the columns are independent).  L is
-// staged in LDS (row stride n + 1); lane l keeps rows l and l + 64 of its
-// column in registers, so each row step is two LDS loads, a VALU wave sum
-// and one update by the owning lane -- no barriers after the staging.
+// One 64-lane workgroup per column of B (the columns are independent); lane
+// l keeps rows l and l + 64 of its column in registers.  Column-oriented
+// substitution: at step i the owner lane finishes x_i (one division), it is
+// broadcast with v_readlane, and every lane removes its contribution from
+// its own rows with one FMA.  The coefficients do not depend on x, so the
+// unrolled loop issues their loads ahead; no shared memory is used.
 constexpr int TRSM_NMAX = 128;
 
 __global__ __launch_bounds__(64) void k_trsm_lower(int n, int m, const double* __restrict__ L,
                                                    int64_t ldl, int trans, double* B, int64_t ldb) {
-    extern __shared__ double sm[];
-    const int ld = n + 1;
-    double* Ls = sm;  // n x ld
     const int l = threadIdx.x, j = blockIdx.x;
-    for (int e = l; e < n * n; e += 64) {
-        const int i = e / n, p = e % n;
-        Ls[i * ld + p] = (p <= i) ? L[(int64_t)i * ldl + p] : 0.0;
-    }
-    double x0 = (l < n) ? B[(int64_t)l * ldb + j] : 0.0;
-    double x1 = (l + 64 < n) ? B[(int64_t)(l + 64) * ldb + j] : 0.0;
-    __syncthreads();
+    const int r0 = l, r1 = l + 64;
+    // rows clamped into the n x n block for the loads (values masked)
+    const int c0r = (r0 < n) ? r0 : n - 1, c1r = (r1 < n) ? r1 : n - 1;
+    double x0 = (r0 < n) ? B[(int64_t)r0 * ldb + j] : 0.0;
+    double x1 = (r1 < n) ? B[(int64_t)r1 * ldb + j] : 0.0;
+#pragma unroll 8
     for (int it = 0; it < n; it++) {
         const int i = trans ? (n - 1 - it) : it;
-        // terms p < i (forward: L[i][p]) or p > i (backward: L[p][i])
-        // LDS indices are clamped into the staged n x n block (values masked)
-        const int r0 = (l < n) ? l : n - 1, r1 = (l + 64 < n) ? l + 64 : n - 1;
-        double t0, t1;
+        // coefficient of x_i in rows r0, r1: L[r][i] for r > i (forward) or
+        // L^T[r][i] = L[i][r] for r < i (backward)
+        double a0, a1;
         if (trans) {
-            const double a0 = Ls[r0 * ld + i], a1 = Ls[r1 * ld + i];
-            t0 = (l > i && l < n) ? a0 * x0 : 0.0;
-            t1 = (l + 64 > i && l + 64 < n) ? a1 * x1 : 0.0;
+            a0 = L[(int64_t)i * ldl + c0r];
+            a1 = L[(int64_t)i * ldl + c1r];
+            a0 = (r0 < i) ? a0 : 0.0;
+            a1 = (r1 < i) ? a1 : 0.0;
         } else {
-            const double a0 = Ls[i * ld + r0], a1 = Ls[i * ld + r1];
-            t0 = (l < i) ? a0 * x0 : 0.0;
-            t1 = (l + 64 < i) ? a1 * x1 : 0.0;
+            a0 = L[(int64_t)c0r * ldl + i];
+            a1 = L[(int64_t)c1r * ldl + i];
+            a0 = (r0 > i && r0 < n) ? a0 : 0.0;
+            a1 = (r1 > i && r1 < n) ? a1 : 0.0;
         }
-        const double s = sum_wave_valu(t0 + t1);
-        const double d = Ls[i * ld + i];
-        if (l == i) x0 = (x0 - s) / d;
-        if (l + 64 == i) x1 = (x1 - s) / d;
+        const double d = L[(int64_t)i * ldl + i];
+        double xi;
+        if (i < 64) {
+            if (l == i) x0 = x0 / d;
+            xi = bcast(x0, i);
+        } else {
+            if (l == i - 64) x1 = x1 / d;
+            xi = bcast(x1, i - 64);
+        }
+        x0 -= a0 * xi;
+        x1 -= a1 * xi;
     }
-    if (l < n) B[(int64_t)l * ldb + j] = x0;
-    if (l + 64 < n) B[(int64_t)(l + 64) * ldb + j] = x1;
+    if (r0 < n) B[(int64_t)r0 * ldb + j] = x0;
+    if (r1 < n) B[(int64_t)r1 * ldb + j] = x1;
 }
 
 __global__ __launch_bounds__(1024) void k_qr_top(int n, const double* __restrict__ Vt, int64_t ldv,
@@ -328,15 +334,7 @@ hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int tra
                              int64_t ldb, hipStream_t st) {
     if (n <= 0 || m <= 0) return hipSuccess;
     if (n > TRSM_NMAX) return hipErrorInvalidValue;
-    const size_t shm = (size_t)n * (n + 1) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_trsm_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL(k_trsm_lower, dim3(m), dim3(64), shm, st, n, m, L, ldl, trans, B, ldb);
+    hipLaunchKernelGGL(k_trsm_lower, dim3(m), dim3(64), 0, st, n, m, L, ldl, trans, B, ldb);
     return hipGetLastError();
 }
 
