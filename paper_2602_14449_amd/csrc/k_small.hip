@@ -147,48 +147,53 @@ __global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __
 //   trans == 1:  L^T X = B (backward substitution; L^T is upper)
 // One 64-lane workgroup per column of B (the columns are independent); lane
 // l keeps rows l and l + 64 of its column in registers.  Column-oriented
-// substitution: at step i the owner lane finishes x_i (one division), it is
-// broadcast with v_readlane, and every lane removes its contribution from
-// its own rows with one FMA.  The coefficients do not depend on x, so the
+// substitution: at step i the owner lane finishes x_i (one multiply by the
+// reciprocal of L_ii, computed up front), it is broadcast with v_readlane,
+// and every lane removes its contribution from its own rows with one FMA.  The coefficients do not depend on x, so the
 // unrolled loop issues their loads ahead; no shared memory is used.
 constexpr int TRSM_NMAX = 128;
 
+template <int TRANS>
 __global__ __launch_bounds__(64) void k_trsm_lower(int n, int m, const double* __restrict__ L,
-                                                   int64_t ldl, int trans, double* B, int64_t ldb) {
+                                                   int64_t ldl, double* B, int64_t ldb) {
     const int l = threadIdx.x, j = blockIdx.x;
     const int r0 = l, r1 = l + 64;
     // rows clamped into the n x n block for the loads (values masked)
     const int c0r = (r0 < n) ? r0 : n - 1, c1r = (r1 < n) ? r1 : n - 1;
     double x0 = (r0 < n) ? B[(int64_t)r0 * ldb + j] : 0.0;
     double x1 = (r1 < n) ? B[(int64_t)r1 * ldb + j] : 0.0;
-#pragma unroll 8
-    for (int it = 0; it < n; it++) {
-        const int i = trans ? (n - 1 - it) : it;
-        // coefficient of x_i in rows r0, r1: L[r][i] for r > i (forward) or
-        // L^T[r][i] = L[i][r] for r < i (backward)
-        double a0, a1;
-        if (trans) {
-            a0 = L[(int64_t)i * ldl + c0r];
-            a1 = L[(int64_t)i * ldl + c1r];
-            a0 = (r0 < i) ? a0 : 0.0;
-            a1 = (r1 < i) ? a1 : 0.0;
-        } else {
-            a0 = L[(int64_t)c0r * ldl + i];
-            a1 = L[(int64_t)c1r * ldl + i];
-            a0 = (r0 > i && r0 < n) ? a0 : 0.0;
-            a1 = (r1 > i && r1 < n) ? a1 : 0.0;
+    // reciprocals of the diagonal entries of the lane's own rows, off the
+    // dependency chain of the substitution
+    const double rd0 = 1.0 / L[(int64_t)c0r * ldl + c0r];
+    const double rd1 = 1.0 / L[(int64_t)c1r * ldl + c1r];
+    // 16 steps at a time: all their coefficient loads first (clamped, so
+    // unconditional), then the substitution steps, which have no branch
+    constexpr int U = 16;
+    for (int it0 = 0; it0 < n; it0 += U) {
+        double a0[U], a1[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int itc = (it0 + u < n) ? it0 + u : n - 1;
+            const int i = TRANS ? (n - 1 - itc) : itc;
+            // coefficient of x_i in rows r0, r1: L[r][i] (forward) or
+            // L^T[r][i] = L[i][r] (backward)
+            a0[u] = TRANS ? L[(int64_t)i * ldl + c0r] : L[(int64_t)c0r * ldl + i];
+            a1[u] = TRANS ? L[(int64_t)i * ldl + c1r] : L[(int64_t)c1r * ldl + i];
         }
-        const double d = L[(int64_t)i * ldl + i];
-        double xi;
-        if (i < 64) {
-            if (l == i) x0 = x0 / d;
-            xi = bcast(x0, i);
-        } else {
-            if (l == i - 64) x1 = x1 / d;
-            xi = bcast(x1, i - 64);
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool valid = it0 + u < n;  // uniform
+            const int itc = valid ? it0 + u : n - 1;
+            const int i = TRANS ? (n - 1 - itc) : itc;
+            // rows below (forward) or above (backward) the pivot take part
+            const bool t0 = valid && (TRANS ? r0 < i : (r0 > i && r0 < n));
+            const bool t1 = valid && (TRANS ? r1 < i : (r1 > i && r1 < n));
+            x0 = (valid && l == i) ? x0 * rd0 : x0;
+            x1 = (valid && l + 64 == i) ? x1 * rd1 : x1;
+            const double xi = bcast((i < 64) ? x0 : x1, i & 63);
+            x0 -= (t0 ? a0[u] : 0.0) * xi;
+            x1 -= (t1 ? a1[u] : 0.0) * xi;
         }
-        x0 -= a0 * xi;
-        x1 -= a1 * xi;
     }
     if (r0 < n) B[(int64_t)r0 * ldb + j] = x0;
     if (r1 < n) B[(int64_t)r1 * ldb + j] = x1;
@@ -334,7 +339,8 @@ hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int tra
                              int64_t ldb, hipStream_t st) {
     if (n <= 0 || m <= 0) return hipSuccess;
     if (n > TRSM_NMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_trsm_lower, dim3(m), dim3(64), 0, st, n, m, L, ldl, trans, B, ldb);
+    if (trans) hipLaunchKernelGGL(k_trsm_lower<1>, dim3(m), dim3(64), 0, st, n, m, L, ldl, B, ldb);
+    else hipLaunchKernelGGL(k_trsm_lower<0>, dim3(m), dim3(64), 0, st, n, m, L, ldl, B, ldb);
     return hipGetLastError();
 }
 
