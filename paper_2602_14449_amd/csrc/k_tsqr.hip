@@ -9,9 +9,19 @@ __global__ __launch_bounds__(NW * 64, 2) void k_tsqr_leaf(TsqrLevel L) {
     leaf_chunk<KP, K0P, PANEL, 0>(L, blockIdx.x);
 }
 
-template <int KP, int K0P, int PANEL>
-__global__ __launch_bounds__(NW * 64, 2) void k_tsqr_form(TsqrLevel L) {
-    form_chunk<KP, K0P, PANEL, 0>(L, blockIdx.x);
+
+// Levels above 0 (no V term): eight wavefronts per chunk, so that a tile
+// stacks four R factors of the level below (fan-in 4, half the levels).
+constexpr int NW_UP = 8;
+
+template <int KP>
+__global__ __launch_bounds__(NW_UP * 64, 1) void k_tsqr_leaf_up(TsqrLevel L) {
+    leaf_chunk<KP, 0, 0, 0, NW_UP>(L, blockIdx.x);
+}
+
+template <int KP>
+__global__ __launch_bounds__(NW_UP * 64, 1) void k_tsqr_form_up(TsqrLevel L) {
+    form_chunk<KP, 0, 0, 0, NW_UP>(L, blockIdx.x);
 }
 
 template <int KP>
@@ -42,17 +52,31 @@ static hipError_t leaf_t(const TsqrLevel& L, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int KP, int K0P, int PANEL>
-static hipError_t form_t(const TsqrLevel& L, hipStream_t st) {
-    const size_t shm = FormLds<KP>::total * sizeof(double);
+template <int KP>
+static hipError_t leaf_up_t(const TsqrLevel& L, hipStream_t st) {
+    const size_t shm = LeafLds<KP, 0, NW_UP>::total * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_form<KP, K0P, PANEL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_leaf_up<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_tsqr_form<KP, K0P, PANEL>), dim3(L.nchunk), dim3(NW * 64), shm, st, L);
+    hipLaunchKernelGGL((k_tsqr_leaf_up<KP>), dim3(L.nchunk), dim3(NW_UP * 64), shm, st, L);
+    return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t form_up_t(const TsqrLevel& L, hipStream_t st) {
+    const size_t shm = FormLds<KP>::total * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tsqr_form_up<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_tsqr_form_up<KP>), dim3(L.nchunk), dim3(NW_UP * 64), shm, st, L);
     return hipGetLastError();
 }
 
@@ -126,17 +150,30 @@ int tsqr_tile_rows(int kp) {
     return kp >= 64 ? Geo<64>::TB : Geo<16>::TB;
 }
 
+int tsqr_tile_rows_up(int kp) {
+    return kp >= 64 ? Geo<64, 0, NW_UP>::TB : Geo<16, 0, NW_UP>::TB;
+}
+
 hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st) {
     if (panel == PANEL_F32X2) TSQR_DISPATCH_LOWP(leaf_t, PANEL_F32X2)
     if (panel == PANEL_BF16) TSQR_DISPATCH_LOWP(leaf_t, PANEL_BF16)
     TSQR_DISPATCH(leaf_t)
 }
 
-hipError_t launch_tsqr_form(int kp, const TsqrLevel& L, hipStream_t st) {
+hipError_t launch_tsqr_leaf_up(int kp, const TsqrLevel& L, hipStream_t st) {
     switch (kp) {
-        case 16: return form_t<16, 0, 0>(L, st);
-        case 32: return form_t<32, 0, 0>(L, st);
-        case 64: return form_t<64, 0, 0>(L, st);
+        case 16: return leaf_up_t<16>(L, st);
+        case 32: return leaf_up_t<32>(L, st);
+        case 64: return leaf_up_t<64>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tsqr_form_up(int kp, const TsqrLevel& L, hipStream_t st) {
+    switch (kp) {
+        case 16: return form_up_t<16>(L, st);
+        case 32: return form_up_t<32>(L, st);
+        case 64: return form_up_t<64>(L, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -114,16 +114,17 @@ hipError_t fill(double* p, int64_t n, double v, hipStream_t st) {
 }
 
 // Level 0 gets up to 512 chunks (two per compute unit), upper levels one
-// tile per chunk; every chunk has at least k rows so that its first tile can
-// be factored on its own.
+// tile per chunk (eight wavefronts: four stacked R factors of the level
+// below); every chunk has at least k rows so that its first tile can be
+// factored on its own.
 void tsqr_plan(int64_t m0, int k, Carve& cv, TsqrPlan& T) {
     T.m = m0;
     T.k = k;
     T.KP = kp_of(k);
     T.lv.clear();
-    const int tb = tsqr_tile_rows(T.KP);
     int64_t m = m0;
     for (int level = 0;; level++) {
+        const int tb = (level == 0) ? tsqr_tile_rows(T.KP) : tsqr_tile_rows_up(T.KP);
         int64_t nc = cdiv(m, tb);
         if (level == 0) nc = std::min<int64_t>(nc, 512);
         nc = std::max<int64_t>(1, std::min<int64_t>(nc, m / std::max(1, k)));
@@ -192,10 +193,10 @@ int tsqr_factor(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, double* 
     const int nl = (int)Ls.size();
     for (int l = 0; l < nl; l++)
         PROF(l == 0 ? "leaf_l0" : "leaf_up", st,
-             launch_tsqr_leaf(T.KP, l == 0 ? k0p : 0, l == 0 ? panel : 0, Ls[l], st));
+             l == 0 ? launch_tsqr_leaf(T.KP, k0p, panel, Ls[l], st) : launch_tsqr_leaf_up(T.KP, Ls[l], st));
     // R with nonnegative diagonal; the top-level Q starts from the sign matrix
     PROF("finish_r", st, launch_finish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
-    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form(T.KP, Ls[l], st));
+    for (int l = nl - 1; l >= 1; l--) PROF("form_up", st, launch_tsqr_form_up(T.KP, Ls[l], st));
     return 0;
 }
 

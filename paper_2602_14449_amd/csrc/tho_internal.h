@@ -171,8 +171,11 @@ hipError_t launch_pack_b(int p, int q, const double* src, int64_t lds, int trans
 // kp in {16, 32, 64}; k0p in {0, 16, 32, 64, 128} (0: no V term); panel
 // 0 = FP64, 1 = FP32 hi + lo, 2 = BF16 for the V products (k0p > 0 only).
 hipError_t launch_tsqr_leaf(int kp, int k0p, int panel, const TsqrLevel& L, hipStream_t st);
-// Formation of a level above 0 (no V term), one workgroup per chunk.
-hipError_t launch_tsqr_form(int kp, const TsqrLevel& L, hipStream_t st);
+// Levels above 0 (no V term): factorization and formation with one
+// workgroup of eight wavefronts per chunk, tiles of tsqr_tile_rows_up(kp).
+int tsqr_tile_rows_up(int kp);
+hipError_t launch_tsqr_leaf_up(int kp, const TsqrLevel& L, hipStream_t st);
+hipError_t launch_tsqr_form_up(int kp, const TsqrLevel& L, hipStream_t st);
 // Two-pass formation of level 0: the per-chunk recurrence of the k x k
 // blocks (overwrites each T_t with -K_t and fills Cfin), then every tile's
 // rows of Q independently.

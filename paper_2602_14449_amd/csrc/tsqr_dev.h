@@ -48,11 +48,11 @@ constexpr int NW = LEAF_WAVES;     // wavefronts per workgroup
 // Tile geometry per column count: the register tile is RB 16-row blocks per
 // wavefront (KP = 64: 2 blocks, so that a wavefront fits in 256 registers
 // and two workgroups share a compute unit; narrower: 4 blocks).
-template <int KP, int RBO = 0>
+template <int KP, int RBO = 0, int NWT = NW>
 struct Geo {
     static constexpr int RB = RBO ? RBO : ((KP >= 64) ? 2 : 4);  // 16-row blocks per wavefront
     static constexpr int RPW = 16 * RB;            // rows per wavefront
-    static constexpr int TB = NW * RPW;            // rows per tile
+    static constexpr int TB = NWT * RPW;           // rows per tile (NWT wavefronts)
 };
 
 // Lane id the compiler cannot treat as loop invariant: per-lane address
@@ -69,10 +69,10 @@ __device__ __forceinline__ int tile_row(int w, int rb, int l, int v) {
     return RPW * w + 16 * rb + drow(l, v);
 }
 
-template <int KP, int RBO = 0>
+template <int KP, int RBO = 0, int NWT = NW>
 struct LeafLds {
     static constexpr int LDT = KP + 1;
-    static constexpr int total = 2 * KP * LDT + Geo<KP, RBO>::TB + 2 * KP + 2 * NW * KP + KP;
+    static constexpr int total = 2 * KP * LDT + Geo<KP, RBO, NWT>::TB + 2 * KP + 2 * NWT * KP + KP;
 };
 
 template <int KP>
@@ -92,7 +92,7 @@ struct FormLds {
 // Returns beta of the last column; for a structured tile the caller stores it
 // into slot(k-1, k-1) after the next workgroup barrier (other wavefronts read
 // that entry as the pivot of the last column until then).
-template <int KP, bool PLAIN, int RBO>
+template <int KP, bool PLAIN, int RBO, int NWT = NW>
 __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][KP / 16], int k, int w, double* xcol,
                                                  double* prow, double* part, double* slot, double* Gm,
                                                  double* taus) {
@@ -142,7 +142,7 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
 #pragma unroll
                     for (int ct = 0; ct < CT; ct++) sc[ct] += xs[rb][v] * x[rb][ct][v];
             const double tot = col_sums<CT>(sc);  // valid in lanes l < KP
-            if (l < KP) part[(pb * NW + w) * KP + l] = tot;
+            if (l < KP) part[(pb * NWT + w) * KP + l] = tot;
         }
         if (PLAIN && w == j / RPW) {
             // publish the pivot row (row j of the tile)
@@ -165,7 +165,7 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
         double dl = 0.0, pl = 0.0;
         if (l < KP) {
 #pragma unroll
-            for (int ww = 0; ww < NW; ww++) dl += part[(pb * NW + ww) * KP + l];
+            for (int ww = 0; ww < NWT; ww++) dl += part[(pb * NWT + ww) * KP + l];
             pl = PLAIN ? prow[pb * KP + l] : slot[j * LDT + l];
         }
         const double sig2 = bcast(dl, j);
@@ -305,12 +305,13 @@ __device__ __forceinline__ void tile_t_factor(double* TG, const double* taus, in
         }
         if constexpr (CT == 4) {
             // pairs of 32: rows {0,1} x columns {2,3}; wavefront w owns block (ia, jb)
-            const int ia = w >> 1, jb = 2 + (w & 1);
+            const int ia = (w >> 1) & 1, jb = 2 + (w & 1);
+            const bool mw = w < 4;  // wavefronts 0..3 own the four blocks
             __syncthreads();
             d4 x = d4zero();
 #pragma unroll
             for (int kb = 2; kb < 4; kb++) {
-                if (kb > jb) continue;  // T_BB is upper triangular
+                if (kb > jb || !mw) continue;  // T_BB is upper triangular
 #pragma unroll
                 for (int s = 0; s < 4; s++) {
                     const int kk = 4 * s + g;
@@ -320,13 +321,15 @@ __device__ __forceinline__ void tile_t_factor(double* TG, const double* taus, in
                     x = mfma(ga, tb, x);
                 }
             }
+            if (mw) {
 #pragma unroll
-            for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = x[v];
+                for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = x[v];
+            }
             __syncthreads();
             d4 y = d4zero();
 #pragma unroll
             for (int ka = 0; ka < 2; ka++) {
-                if (ka < ia) continue;  // T_AA is upper triangular
+                if (ka < ia || !mw) continue;  // T_AA is upper triangular
 #pragma unroll
                 for (int s = 0; s < 4; s++) {
                     const int kk = 4 * s + g;
@@ -336,31 +339,33 @@ __device__ __forceinline__ void tile_t_factor(double* TG, const double* taus, in
                 }
             }
             __syncthreads();  // every X block has been read
+            if (mw) {
 #pragma unroll
-            for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = -y[v];
+                for (int v = 0; v < 4; v++) TG[(16 * ia + g + 4 * v) * LDT + 16 * jb + cl] = -y[v];
+            }
         }
     }
 }
 
 }  // namespace
 
-template <int KP, int K0P, int PANEL, int RBO>
+template <int KP, int K0P, int PANEL, int RBO, int NWT = NW>
 __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
-    constexpr int RB = Geo<KP, RBO>::RB, RPW = Geo<KP, RBO>::RPW, TB = Geo<KP, RBO>::TB;
+    constexpr int RB = Geo<KP, RBO, NWT>::RB, RPW = Geo<KP, RBO, NWT>::RPW, TB = Geo<KP, RBO, NWT>::TB;
     constexpr int CT = KP / 16;
     constexpr int LDT = KP + 1;
     constexpr bool HASV = K0P > 0;
     constexpr int KS0 = (K0P > 0) ? K0P / 4 : 1;
     constexpr int MT0 = (K0P > 0) ? K0P / 16 : 1;  // 16-column blocks of N^T
-    constexpr int NJW = (MT0 + NW - 1) / NW;        // ... owned per wavefront
+    constexpr int NJW = (MT0 + NWT - 1) / NWT;      // ... owned per wavefront
 
     extern __shared__ double sm[];
     double* TG = sm;                    // KP x LDT: T (upper) and Gm (strict lower)
     double* slot = TG + KP * LDT;       // KP x LDT: running R of the chunk
     double* xcol = slot + KP * LDT;     // TB: pivot column, RPW rows per wavefront
     double* prow = xcol + TB;           // 2 x KP: pivot row of the plain tile
-    double* part = prow + 2 * KP;       // 2 x NW x KP: partial dot products
-    double* taus = part + 2 * NW * KP;  // KP: tau of each reflector
+    double* part = prow + 2 * KP;        // 2 x NWT x KP: partial dot products
+    double* taus = part + 2 * NWT * KP;  // KP: tau of each reflector
 
     const int tid = threadIdx.x, w = tid >> 6;
     const int k = L.k;
@@ -370,7 +375,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
     const int ntiles = (int)((cr1 - cr0 + TB - 1) / TB);
 
     // The running N_c^T (KP x K0P, = Q_chunk^T V_chunk) lives in L.Nc[c];
-    // wavefront w owns its 16-column blocks nj = w, w + NW, ... (all rows) and
+    // wavefront w owns its 16-column blocks nj = w, w + NWT, ... (all rows) and
     // is the only one to read or write them.
     double* NT = (HASV && k0 > 0) ? L.Nc + (int64_t)c * KP * K0P : nullptr;
 
@@ -439,8 +444,8 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         PHASE_TS(t, 1);
         // ---- Householder QR of the tile (plain) or of [R; tile] (structured)
         double beta_last;
-        if (plain) beta_last = householder_tile<KP, true, RBO>(x, k, w, xcol, prow, part, slot, TG, taus);
-        else beta_last = householder_tile<KP, false, RBO>(x, k, w, xcol, prow, part, slot, TG, taus);
+        if (plain) beta_last = householder_tile<KP, true, RBO, NWT>(x, k, w, xcol, prow, part, slot, TG, taus);
+        else beta_last = householder_tile<KP, false, RBO, NWT>(x, k, w, xcol, prow, part, slot, TG, taus);
         __syncthreads();
         // row k-1 of the slot has no trailing columns; only its diagonal changes
         if (!plain && w == 0 && k > 0 && (threadIdx.x & 63) == k - 1) slot[(k - 1) * LDT + (k - 1)] = beta_last;
@@ -514,7 +519,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                 for (int q = 0; q < NJW; q++)
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
+                        const int r = 16 * mi + drow(l, v), cc = 16 * (w + NWT * q) + cl;
                         sacc[mi][q][v] = (!plain && cc < K0P) ? NT[r * K0P + cc] : 0.0;
                     }
             // B^T = Y^T V over the tile rows (4 rows per K-step)
@@ -532,7 +537,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     }
 #pragma unroll
                     for (int q = 0; q < NJW; q++) {
-                        const int vc = 16 * (w + NW * q) + cl;
+                        const int vc = 16 * (w + NWT * q) + cl;
                         vb[u][q] = (ok && vc < k0) ? Vt[row * ldv + vc] : 0.0;
                     }
                 }
@@ -571,7 +576,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     for (int q = 0; q < NJW; q++)
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
+                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NWT * q) + cl;
                             if (cc < K0P) NT[r * K0P + cc] -= dacc[mi][q][v];
                         }
             } else {
@@ -601,7 +606,7 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
                     for (int q = 0; q < NJW; q++)
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
-                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NW * q) + cl;
+                            const int r = 16 * mi + drow(l, v), cc = 16 * (w + NWT * q) + cl;
                             const double vt = (r < k && cc < k0) ? Vt[r * ldv + cc] : 0.0;
                             if (cc < K0P) NT[r * K0P + cc] = vt - eacc[mi][q][v];
                         }
@@ -626,16 +631,16 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
 //   plain tile 0:       K = T_0 (Y_0[0:k]^T C),   rows = [C; 0] - Y_0 K
 // Level 0 adds V N (formation of Q in Algorithm 1: Q_low = Q_ + V_low N).
 // Output rows overwrite the Householder vectors in place.
-template <int KP, int K0P, int PANEL, int RBO>
+template <int KP, int K0P, int PANEL, int RBO, int NWT = NW>
 __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
-    constexpr int RB = Geo<KP, RBO>::RB, RPW = Geo<KP, RBO>::RPW, TB = Geo<KP, RBO>::TB;
+    constexpr int RB = Geo<KP, RBO, NWT>::RB, RPW = Geo<KP, RBO, NWT>::RPW, TB = Geo<KP, RBO, NWT>::TB;
     constexpr int CT = KP / 16;
     constexpr int LDT = KP + 1;
     constexpr bool HASV = K0P > 0;
     constexpr int KS0 = (K0P > 0) ? K0P / 4 : 1;
     constexpr int KSK = KP / 4;
     constexpr int NTK = CT * CT;
-    constexpr int NTKW = (NTK + NW - 1) / NW;
+    constexpr int NTKW = (NTK + NWT - 1) / NWT;
 
     extern __shared__ double sm[];
     double* Cm = sm;              // KP x LDT
@@ -677,7 +682,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
             for (int s = 0; s < KSK; s++)
 #pragma unroll
                 for (int i = 0; i < NTKW; i++) {
-                    const int id = w + NW * i;
+                    const int id = w + NWT * i;
                     if (id < NTK) {
                         const int mi = id / CT, nj = id % CT;
                         const int yr = 4 * s + g, yc = 16 * mi + cl;
@@ -687,7 +692,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
                 }
 #pragma unroll
             for (int i = 0; i < NTKW; i++) {
-                const int id = w + NW * i;
+                const int id = w + NWT * i;
                 if (id < NTK) {
                     const int mi = id / CT, nj = id % CT;
 #pragma unroll
@@ -706,7 +711,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
         for (int s = 0; s < KSK; s++)
 #pragma unroll
             for (int i = 0; i < NTKW; i++) {
-                const int id = w + NW * i;
+                const int id = w + NWT * i;
                 if (id < NTK) {
                     const int mi = id / CT, nj = id % CT;
                     const double a = Tg[(16 * mi + cl) * KP + g * KSK + s];
@@ -716,7 +721,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NTKW; i++) {
-            const int id = w + NW * i;
+            const int id = w + NWT * i;
             if (id < NTK) {
                 const int mi = id / CT, nj = id % CT;
 #pragma unroll
