@@ -287,9 +287,12 @@ int tho_batched_plan_create(int32_t count, const tho_problem_t* probs, void* ws,
         PCHK(hipEventCreate(&e1));
         float best = 1e30f;
         for (int rbo : {4, 2})
-            for (int grid : {2 * cus, cus}) {
+            for (int grid : {4 * cus, 3 * cus, 2 * cus, cus}) {
+                // one untimed launch (cold caches, first use of the variant),
+                // then the best of three
+                if (int r = launch_all(P, rbo, grid, P->cs)) return fail(r);
                 float t = 1e30f;
-                for (int rep = 0; rep < 2; rep++) {
+                for (int rep = 0; rep < 3; rep++) {
                     PCHK(hipEventRecord(e0, P->cs));
                     if (int r = launch_all(P, rbo, grid, P->cs)) return fail(r);
                     PCHK(hipEventRecord(e1, P->cs));
