@@ -106,23 +106,45 @@ __global__ __launch_bounds__(256) void k_xty_partial(
     }
 }
 
-// out[i] = sum over parts of part[p][i], in part order (deterministic).
-__global__ void k_reduce_parts(int nparts, int64_t elems, const double* __restrict__ part,
-                               double* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= elems) return;
+// out[i] = sum over parts of part[p][i] in a fixed order (deterministic).
+// A workgroup owns 64 consecutive elements (one per lane) and its 16
+// wavefronts each sum a contiguous range of the parts, so every load of a
+// wavefront is one coalesced 512-byte row piece and the whole chip takes
+// part; the 16 range sums are added in LDS in range order.
+constexpr int RED_WAVES = 16;
+
+__global__ __launch_bounds__(64 * RED_WAVES) void k_reduce_parts(int nparts, int64_t elems,
+                                                                 const double* __restrict__ part,
+                                                                 double* __restrict__ out) {
+    __shared__ double red[RED_WAVES][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int per = (nparts + RED_WAVES - 1) / RED_WAVES;
+    const int p0 = min(nparts, w * per), p1 = min(nparts, p0 + per);
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int p = 0;
-    for (; p + 8 <= nparts; p += 8)
+    if (i < elems) {
+        int p = p0;
+        for (; p + 8 <= p1; p += 8)
 #pragma unroll
-        for (int u = 0; u < 8; u++) s[u] += part[(int64_t)(p + u) * elems + i];
-    for (; p < nparts; p++) s[0] += part[(int64_t)p * elems + i];
-    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+            for (int u = 0; u < 8; u++) s[u] += part[(int64_t)(p + u) * elems + i];
+        for (; p < p1; p++) s[0] += part[(int64_t)p * elems + i];
+    }
+    red[w][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    __syncthreads();
+    if (w == 0 && i < elems) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int q = 1; q < RED_WAVES; q++) t += red[q][lane];
+        out[i] = t;
+    }
 }
 
 // D = alpha op(A) op(B) + beta C for small matrices, one thread per output.
 // op(A) is M x K: A[i*lda + p] (or A[p*lda + i] if ta); op(B) is K x N.
-// C may alias D (elementwise read-then-write by the same thread).
+// C may alias D (elementwise read-then-write by the same thread).  The
+// operand strides are fixed before the loop, so the unrolled body has no
+// branches and issues the loads of 16 steps ahead of their FMAs (the sum
+// is still taken in order p = 0, 1, ...).
 __global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __restrict__ A,
                              int64_t lda, int ta, const double* __restrict__ B, int64_t ldb,
                              int tb, double beta, const double* C, int64_t ldc, double* D,
@@ -130,12 +152,12 @@ __global__ void k_small_gemm(int M, int N, int K, double alpha, const double* __
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)M * N) return;
     const int i = (int)(t / N), j = (int)(t % N);
+    const int64_t ap = ta ? lda : 1, bp = tb ? 1 : ldb;
+    const double* a_row = A + (ta ? (int64_t)i : (int64_t)i * lda);
+    const double* b_col = B + (tb ? (int64_t)j * ldb : (int64_t)j);
     double s = 0.0;
-    for (int p = 0; p < K; p++) {
-        const double a = ta ? A[(int64_t)p * lda + i] : A[(int64_t)i * lda + p];
-        const double b = tb ? B[(int64_t)j * ldb + p] : B[(int64_t)p * ldb + j];
-        s = fma(a, b, s);
-    }
+#pragma unroll 16
+    for (int p = 0; p < K; p++) s = fma(a_row[p * ap], b_col[p * bp], s);
     double r = alpha * s;
     if (beta != 0.0) r = fma(beta, C[(int64_t)i * ldc + j], r);
     D[(int64_t)i * ldd + j] = r;
@@ -318,9 +340,10 @@ hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, in
 
 hipError_t launch_reduce_parts(int nparts, int64_t elems, const double* part, double* out,
                                hipStream_t st) {
-    const int bs = 256;
-    const int64_t nb = (elems + bs - 1) / bs;
-    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)nb), dim3(bs), 0, st, nparts, elems, part, out);
+    if (elems <= 0) return hipSuccess;
+    const int64_t nb = (elems + 63) / 64;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)nb), dim3(64 * RED_WAVES), 0, st, nparts, elems, part,
+                       out);
     return hipGetLastError();
 }
 
