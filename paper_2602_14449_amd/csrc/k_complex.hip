@@ -381,43 +381,57 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
 }
 
 // D = alpha op(A) op(B) + beta C (complex, small); op: 0 none, 1 transpose,
-// 2 conjugate transpose.  C may alias D.
+// 2 conjugate transpose.  C may alias D.  The operand strides and the sign
+// of the conjugation are fixed before the loop, so the unrolled body has no
+// branches and issues the loads of 8 steps ahead (the sum is still taken in
+// order p = 0, 1, ...).
 __global__ void k_zgemm(int M, int N, int K, cplx alpha, const cplx* A, int64_t lda, int opa, const cplx* B,
                         int64_t ldb, int opb, cplx beta, const cplx* C, int64_t ldc, cplx* D, int64_t ldd) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)M * N) return;
     const int i = (int)(t / N), j = (int)(t % N);
+    const int64_t ap = opa ? lda : 1, bp = opb ? 1 : ldb;
+    const cplx* a_row = A + (opa ? (int64_t)i : (int64_t)i * lda);
+    const cplx* b_col = B + (opb ? (int64_t)j * ldb : (int64_t)j);
+    const double sa = (opa == 2) ? -1.0 : 1.0, sb = (opb == 2) ? -1.0 : 1.0;
     cplx s = cmk(0.0, 0.0);
+#pragma unroll 8
     for (int p = 0; p < K; p++) {
-        cplx a = opa ? A[(int64_t)p * lda + i] : A[(int64_t)i * lda + p];
-        if (opa == 2) a = cconj(a);
-        cplx b = opb ? B[(int64_t)j * ldb + p] : B[(int64_t)p * ldb + j];
-        if (opb == 2) b = cconj(b);
-        s = cadd(s, cmul(a, b));
+        const cplx a0 = a_row[p * ap], b0 = b_col[p * bp];
+        s = cadd(s, cmul(cmk(a0.re, sa * a0.im), cmk(b0.re, sb * b0.im)));
     }
     cplx r = cmul(alpha, s);
     if (beta.re != 0.0 || beta.im != 0.0) r = cadd(r, cmul(beta, C[(int64_t)i * ldc + j]));
     D[(int64_t)i * ldd + j] = r;
 }
 
-// In-place solve with lower-triangular L (n x n) on B (n x m):
-//   mode 0: L X = B;  mode 2: L^H X = B.  One column of B per thread.
-__global__ void k_ztrsm(int n, int m, const cplx* L, int64_t ldl, int mode, cplx* B, int64_t ldb) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    if (mode == 0) {
-        for (int i = 0; i < n; i++) {
-            cplx s = B[(int64_t)i * ldb + j];
-            for (int p = 0; p < i; p++) s = csub(s, cmul(L[(int64_t)i * ldl + p], B[(int64_t)p * ldb + j]));
-            B[(int64_t)i * ldb + j] = cdiv(s, L[(int64_t)i * ldl + i]);
-        }
-    } else {
-        for (int i = n - 1; i >= 0; i--) {
-            cplx s = B[(int64_t)i * ldb + j];
-            for (int p = i + 1; p < n; p++) s = csub(s, cmulc(L[(int64_t)p * ldl + i], B[(int64_t)p * ldb + j]));
-            B[(int64_t)i * ldb + j] = cdiv(s, cconj(L[(int64_t)i * ldl + i]));
-        }
+// In-place solve with lower-triangular L (n x n, n <= 64) on B (n x m):
+//   mode 0: L X = B;  mode 2: L^H X = B.
+// One 64-lane workgroup per column of B; lane l keeps row l in registers.
+// Column-oriented substitution: at step i the owner lane finishes x_i,
+// v_readlane broadcasts it, and every lane whose row depends on x_i removes
+// its contribution.  The coefficients do not depend on x, so the unrolled
+// loop issues their loads ahead of the substitution; no shared memory.
+constexpr int ZTRSM_NMAX = 64;
+
+__global__ __launch_bounds__(64) void k_ztrsm(int n, int m, const cplx* __restrict__ L, int64_t ldl, int mode,
+                                              cplx* B, int64_t ldb) {
+    const int l = threadIdx.x, j = blockIdx.x;
+    const int lc = (l < n) ? l : n - 1;  // row clamped into the block for the loads
+    cplx x = (l < n) ? B[(int64_t)l * ldb + j] : cmk(0.0, 0.0);
+    const cplx d = L[(int64_t)lc * ldl + lc];
+    const cplx dd = mode ? cconj(d) : d;
+#pragma unroll 16
+    for (int it = 0; it < n; it++) {
+        const int i = mode ? (n - 1 - it) : it;
+        // coefficient of x_i in row l: L[l][i] (mode 0) or (L^H)[l][i] = conj(L[i][l])
+        const cplx a = mode ? cconj(L[(int64_t)i * ldl + lc]) : L[(int64_t)lc * ldl + i];
+        if (l == i) x = cdiv(x, dd);
+        const cplx xi = cmk(bcast(x.re, i), bcast(x.im, i));
+        const bool t = mode ? (l < i) : (l > i && l < n);
+        if (t) x = csub(x, cmul(a, xi));
     }
+    if (l < n) B[(int64_t)l * ldb + j] = x;
 }
 
 // From the real-view reduction Cr = X_ri^T Y_ri (2p x 2q real, ld ldc):
@@ -548,7 +562,8 @@ hipError_t launch_zgemm(int M, int N, int K, double ar, double ai, const void* A
 
 hipError_t launch_ztrsm(int n, int m, const void* L, int64_t ldl, int mode, void* B, int64_t ldb, hipStream_t st) {
     if (n <= 0 || m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ztrsm, dim3((m + 63) / 64), dim3(64), 0, st, n, m, (const cplx*)L, ldl, mode, (cplx*)B, ldb);
+    if (n > ZTRSM_NMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ztrsm, dim3(m), dim3(64), 0, st, n, m, (const cplx*)L, ldl, mode, (cplx*)B, ldb);
     return hipGetLastError();
 }
 

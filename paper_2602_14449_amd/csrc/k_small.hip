@@ -249,8 +249,11 @@ __global__ void k_finish_r(int k, int KP, const double* __restrict__ Rin, int64_
 // prod[c] = N_c G_c (K0P x KP): N_c^T is stored (KP x K0P) in NcT[c]; G_c
 // is KP x KP, rows of ld ldg starting at row c*grow_stride of Gbase (only
 // the first k rows/cols are meaningful).  One block per chunk; both small
-// operands are staged in LDS.
-__global__ void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ NcT,
+// operands are staged in LDS.  Each thread owns 4 x 4 patches of the output
+// (rows 4*pi .. 4*pi+3, columns pj + (KP/4)*c), so one LDS read serves four
+// FMAs; every output is summed over p in order.  K0P and KP are multiples of
+// 16.
+__global__ __launch_bounds__(256) void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ NcT,
                              const double* __restrict__ Gbase, int64_t ldg, int64_t grow_stride,
                              double* __restrict__ prod) {
     __shared__ double Ns[64 * 129];  // N_c^T, KP x (K0P + 1)
@@ -265,11 +268,29 @@ __global__ void k_chunk_prod(int K0P, int KP, int k, const double* __restrict__ 
         Gs[i * (KP + 1) + j] = (i < k && j < k) ? G[(int64_t)i * ldg + j] : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < K0P * KP; e += blockDim.x) {
-        const int i = e / KP, j = e % KP;
-        double s = 0.0;
-        for (int p = 0; p < k; p++) s = fma(Ns[p * (K0P + 1) + i], Gs[p * (KP + 1) + j], s);
-        out[e] = s;
+    const int CQ = KP / 4, npatch = (K0P / 4) * CQ;
+    for (int pe = threadIdx.x; pe < npatch; pe += blockDim.x) {
+        const int pi = pe / CQ, pj = pe % CQ;
+        double acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) acc[r][c] = 0.0;
+        for (int p = 0; p < k; p++) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) a[r] = Ns[p * (K0P + 1) + 4 * pi + r];
+#pragma unroll
+            for (int c = 0; c < 4; c++) b[c] = Gs[p * (KP + 1) + pj + CQ * c];
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) out[(4 * pi + r) * KP + pj + CQ * c] = acc[r][c];
     }
 }
 

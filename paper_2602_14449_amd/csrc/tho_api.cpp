@@ -85,28 +85,6 @@ int check_io(int64_t k0, int64_t k, const void* V, int64_t ldv, const void* A, i
 
 namespace {
 
-// Side stream (default priority) and two events per host thread and device,
-// used to run the k0 x k0 QR concurrently with the first reduction.
-struct Fork {
-    bool ok = false;
-    hipStream_t side = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
-
-Fork& fork_for_thread() {
-    thread_local std::vector<Fork> forks;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    if ((int)forks.size() <= dev) forks.resize(dev + 1);
-    Fork& f = forks[dev];
-    if (!f.ok) {
-        f.ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess &&
-               hipEventCreateWithFlags(&f.ev0, hipEventDisableTiming) == hipSuccess &&
-               hipEventCreateWithFlags(&f.ev1, hipEventDisableTiming) == hipSuccess;
-    }
-    return f;
-}
-
 // Launch sequence of Algorithm 1 (second choice of P) on validated
 // arguments; ws holds at least two_stage_bytes(n, k0, k).
 int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv, const double* A, int64_t lda,

@@ -155,10 +155,18 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
     if (k0 > 0) {
         // P and T again, then Z, N and the N adjoint from three
         // reductions over all rows:  C_X = V^T X for X = A, Q, gQ.
-        PROF("qr_top", st, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, st));
+        // The QR of V_top runs on a side stream beside the reductions and is
+        // joined before the first use of P and T.
+        Fork& f = fork_for_thread();
+        if (!f.ok) return set_err(THO_E_HIP, "could not create the side stream");
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        PROF("qr_top", f.side, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, f.side));
+        HIPCHK(hipEventRecord(f.ev1, f.side));
         if ((rc = xty(P.xp, n, V, ldv, ik0, A, lda, ik, P.part, P.CA, st, "xty_partial"))) return rc;
         if ((rc = xty(P.xp, n, V, ldv, ik0, Q, ldq, ik, P.part, P.CQ, st, "xty_partial"))) return rc;
         if ((rc = xty(P.xp, n, V, ldv, ik0, gQ, ldgq, ik, P.part, P.CG, st, "xty_partial"))) return rc;
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
         // Z = T^{-T} W^T A,  W^T A = P^T A_top - V^T A
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.CA, KP, P.Z, KP, st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Z, KP, st));

@@ -195,10 +195,18 @@ int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv
     const dcplx* X0 = A + k0 * lda;  // bottom block, or its update
     int64_t ldx0 = lda;
     if (k0 > 0) {
-        // P = -Q1, T = I + R1^H from V_top = Q1 R1 (real diag R1 >= 0)
-        PROF("zqr_top", st, launch_zqr_top(ik0, V, ldv, P.Pm, P.Tm, st));
+        // P = -Q1, T = I + R1^H from V_top = Q1 R1 (real diag R1 >= 0), on a
+        // side stream concurrently with the reduction V^H A over all n rows;
+        // joined before the first use of P and T
+        Fork& f = fork_for_thread();
+        if (!f.ok) return set_err(THO_E_HIP, "could not create the side stream");
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        PROF("zqr_top", f.side, launch_zqr_top(ik0, V, ldv, P.Pm, P.Tm, f.side));
+        HIPCHK(hipEventRecord(f.ev1, f.side));
         // W^H A = P^H A_top - V^H A ;  Z = T^{-H} W^H A
         if ((rc = zxty(P.xa, n, V, ldv, ik0, A, lda, ik, 1.0, P.C, k, st))) return rc;
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 2, A, lda, 0, -1, 0, P.C, k, P.Z, k, st));
         PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 2, P.Z, k, st));
         // A1_top = A_top - (P - V_top) Z ;  S = P^H A1_top

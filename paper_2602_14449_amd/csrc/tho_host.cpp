@@ -239,4 +239,18 @@ int xty(const XtyPlan& xp, int64_t nrows, const double* X, int64_t ldx, int p, c
     return 0;
 }
 
+Fork& fork_for_thread() {
+    thread_local std::vector<Fork> forks;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if ((int)forks.size() <= dev) forks.resize(dev + 1);
+    Fork& f = forks[dev];
+    if (!f.ok) {
+        f.ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&f.ev0, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&f.ev1, hipEventDisableTiming) == hipSuccess;
+    }
+    return f;
+}
+
 }  // namespace tho

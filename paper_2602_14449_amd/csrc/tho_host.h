@@ -142,4 +142,14 @@ size_t zhhqr_bytes(int64_t n, int64_t k0, int64_t k);
 int run_zhhqr(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
               int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st);
 
+// Side stream (default priority) and two events per host thread and device:
+// the k0 x k0 QR of the top block runs on it beside the first reduction, and
+// the level-0 formation chain beside the products that feed the formation.
+struct Fork {
+    bool ok = false;
+    hipStream_t side = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+Fork& fork_for_thread();
+
 }  // namespace tho
