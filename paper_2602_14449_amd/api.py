@@ -24,12 +24,33 @@ def _dtype_code(t):
 
 
 def _ld(t, name):
-    """Row stride of a row-major 2-D tensor with unit column stride."""
+    """Row stride of a row-major 2-D tensor with unit column stride.
+
+    Rows must not overlap: a tensor with more than one row needs
+    stride(0) >= shape[1] (an expanded or otherwise self-overlapping view
+    would make the kernels read or write past its storage)."""
     if t.dim() != 2:
         raise ValueError("%s must be 2-D" % name)
     if t.stride(1) != 1 and t.shape[1] > 1:
         raise ValueError("%s must have unit column stride" % name)
+    if t.shape[0] > 1 and t.shape[1] > 0 and t.stride(0) < t.shape[1]:
+        raise ValueError("%s has overlapping rows (row stride %d < %d columns); pass a contiguous tensor"
+                         % (name, t.stride(0), t.shape[1]))
     return max(t.stride(0), t.shape[1], 1)
+
+
+def _check_out(t, shape, like, name):
+    """An output tensor supplied by the caller must match exactly."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if t.dtype != like.dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, like.dtype, t.dtype))
+    if t.device != like.device:
+        raise ValueError("%s must be on %s, got %s" % (name, like.device, t.device))
+    _ld(t, name)
+    return t
 
 
 def _ptr(t, nonempty=True):
@@ -41,27 +62,45 @@ def _stream(dev):
 
 
 def _check_inputs(V, A):
-    if not (V.is_cuda and A.is_cuda):
-        raise ValueError("V and A must be GPU tensors")
+    if not (isinstance(V, torch.Tensor) and isinstance(A, torch.Tensor)):
+        raise TypeError("V and A must be tensors")
+    if V.dim() != 2 or A.dim() != 2:
+        raise ValueError("V and A must be 2-D")
     if V.dtype != A.dtype:
         raise TypeError("V and A must have the same dtype")
     if V.shape[0] != A.shape[0]:
         raise ValueError("V and A must have the same number of rows")
-    return _dtype_code(A), V.shape[0], V.shape[1], A.shape[1]
+    code = _dtype_code(A)
+    _ld(V, "V")
+    _ld(A, "A")
+    if not (V.is_cuda and A.is_cuda):
+        raise ValueError("V and A must be GPU tensors")
+    if V.device != A.device:
+        raise ValueError("V and A must be on the same GPU")
+    return code, V.shape[0], V.shape[1], A.shape[1]
 
 
 def _outputs(out, n, k0, k, like):
     if out is not None:
-        return out
+        if len(out) != 3:
+            raise ValueError("out must be a tuple (Q, R, S)")
+        Q, R, S = out
+        return (_check_out(Q, (n, k), like, "out Q"), _check_out(R, (k, k), like, "out R"),
+                _check_out(S, (k0, k), like, "out S"))
     return (torch.empty((n, k), dtype=like.dtype, device=like.device),
             torch.empty((k, k), dtype=like.dtype, device=like.device),
             torch.empty((k0, k), dtype=like.dtype, device=like.device))
 
 
 def _workspace(nbytes, workspace, dev):
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    return workspace
+    """A caller workspace is used when it is a byte tensor on `dev` that is
+    large enough and contiguous; otherwise a new one is allocated."""
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or workspace.device != dev or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on %s" % dev)
+        if workspace.numel() >= nbytes:
+            return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
 
 
 def workspace_bytes(n, k0, k, dtype=torch.float64, panel="fp64"):
@@ -145,6 +184,12 @@ def two_stage_backward(V, A, Q, R, gQ, gR, gS=None, *, workspace=None):
     """Adjoint of (V, A) -> (Q, R, S): returns (dV, dA) for the loss
     gradients gQ = dl/dQ, gR = dl/dR (upper triangle used), gS = dl/dS."""
     code, n, k0, k = _check_inputs(V, A)
+    _check_out(Q, (n, k), A, "Q")
+    _check_out(R, (k, k), A, "R")
+    _check_out(gQ, (n, k), A, "gQ")
+    _check_out(gR, (k, k), A, "gR")
+    if gS is not None:
+        _check_out(gS, (k0, k), A, "gS")
     dV = torch.empty((n, k0), dtype=A.dtype, device=A.device)
     dA = torch.empty((n, k), dtype=A.dtype, device=A.device)
     o = _opts()

@@ -45,26 +45,29 @@ def test_bcgs_parity(n, k0, k, proj, rounds):
 
 
 def test_bcgs_table1_pattern():
-    # Table 1 on the eq. (2) matrices: one projection and one QR loses
-    # orthogonality completely, three projections or three rounds reach
-    # rounding level.  The partial losses printed for (2,1) and (1,2)
-    # (9.8e-2, 7.0e-2) are set by the rounding order of the 1e-30-scaled
-    # products (MATLAB's); fused multiply-adds on the GPU round differently,
-    # so for those rows only boundedness is checked and the value printed.
+    # Table 1 on the eq. (2) matrices.  Rows 1, 4 and 5 are pinned: one
+    # projection and one QR loses orthogonality completely, three projections
+    # or three rounds reach rounding level.  Rows 2 and 3 are informational:
+    # their printed partial losses (9.8e-2, 7.0e-2) are set by the rounding
+    # order of the 1e-30-scaled products (MATLAB's); fused multiply-adds on
+    # the GPU round differently, so only what holds for any rounding is
+    # asserted there -- the intra-block QR is Householder, so Q^T Q = I to
+    # rounding whatever V^T Q is, and the residual is at rounding level.
     require_gpu()
+    from oracle import orth_parts
     here = os.path.dirname(os.path.abspath(__file__))
     gold = json.load(open(os.path.join(here, "golden", "table1_bcgs.json")))
     V, A = W.example2()
     for row in gold["rows"]:
         Q, R, S = _run(V, A, row["proj"], row["rounds"])
         loss = orth_loss(V, Q)
-        print(row["procedure"], "printed", row["printed"], "gpu", loss)
+        vq, qq = orth_parts(V, Q)
+        print(row["procedure"], "printed", row["printed"], "gpu", loss, "||V^TQ||", vq, "||Q^TQ-I||", qq)
         if row["printed"] >= 0.5:
             assert loss >= 0.5
-        elif row["printed"] > 1e-10:
-            assert loss < 1.5
-        else:
+        elif row["printed"] < 1e-10:
             assert loss < 1e-14
+        assert qq < 1e-14
         assert rel_residual(V, A, Q, R, S) < 1e-14
 
 

@@ -42,6 +42,17 @@ def _check_parity(V, A, tol=1e-10, inv=1e-12):
     return Qg, Rg, Sg
 
 
+def _col_tol(R):
+    """Per-column tolerance max(1e-10, 16 u kappa_j) with
+    kappa_j = ||A'||_2 / sigma_min(A'[:, :j+1]) = ||R||_2 / sigma_min(R[:j+1, :j+1])
+    (A' = Q R, the updated bottom block; two correct FP64 QRs of an
+    ill-conditioned matrix differ in column j in proportion to kappa_j)."""
+    k = R.shape[0]
+    sv = [np.linalg.svd(R[:j + 1, :j + 1], compute_uv=False)[-1] for j in range(k)]
+    kap = np.linalg.norm(R, 2) / np.maximum(sv, 1e-300)
+    return np.maximum(1e-10, 16 * 2.0 ** -53 * kap)
+
+
 def test_worked_example_eq2():
     require_gpu()
     V, A = W.example2()
@@ -83,12 +94,7 @@ def test_graded_condition_1e8():
     V, A = W.graded(n=1 << 16, k0=64, k=32, cond=1e8, seed_cfg=12)
     Qg, Rg, Sg = _run(V, A)
     Qo, Ro, So = oracle_two_stage(V, A)
-    # per-column tolerance max(1e-10, 16 u kappa_j) (two correct FP64 QRs of
-    # an ill-conditioned matrix differ in proportion to kappa_j)
-    Ap = Qo @ Ro
-    sv = [np.linalg.svd(Ap[:, :j + 1], compute_uv=False)[-1] for j in range(Ap.shape[1])]
-    kap = np.linalg.norm(Ap, 2) / np.maximum(sv, 1e-300)
-    tolj = np.maximum(1e-10, 16 * 2.0 ** -53 * kap)
+    tolj = _col_tol(Ro)
     err = np.max(np.abs(Qg - Qo), axis=0)
     assert np.all(err <= tolj), (err / tolj).max()
     assert orth_loss(V, Qg) < 1e-12
@@ -141,13 +147,16 @@ def test_deterministic(n, k0, k):
     assert np.abs(B.T @ B - np.eye(k0 + k)).max() < 1e-12
 
 
-def test_full_size_graded_properties():
-    # n = 2^22, k0 = 128, k = 64: invariants at the full size of the graded
-    # workload, in the launch configuration the bench times
+@pytest.mark.timeout(600)
+def test_full_size_graded_parity():
+    # n = 2^22, k0 = 128, k = 64 (the graded workload, cond(A) = 1e8) in the
+    # launch configuration the bench times: Q, R and S element-wise against
+    # the oracle's Algorithm 1 on the same inputs, plus the invariants
     require_gpu()
-    from gpu_util import gpu_gram, herm_norm2
     import paper_2602_14449_amd as tho
+    from oracle import orth_parts
     n, k0, k = 1 << 22, 128, 64
+    print("full-size graded parity n=%d k0=%d k=%d" % (n, k0, k), flush=True)
     g = torch.Generator(device="cuda").manual_seed(5)
     V, _ = torch.linalg.qr(torch.randn(n, k0, dtype=torch.float64, device="cuda", generator=g))
     X, _ = torch.linalg.qr(torch.randn(n, k, dtype=torch.float64, device="cuda", generator=g))
@@ -155,17 +164,24 @@ def test_full_size_graded_properties():
     s = 10.0 ** (-8.0 * torch.arange(k, dtype=torch.float64, device="cuda") / (k - 1))
     A = (X * s[None, :]) @ Y.T.contiguous()
     del X
-    Q, R, S = tho.two_stage(V.contiguous(), A.contiguous())
-    B = torch.cat([V, Q], 1)
-    G = gpu_gram(B).cpu().numpy()
-    loss = herm_norm2(G - np.eye(k0 + k))
-    E = A - V @ S - Q @ R
-    res = np.sqrt(herm_norm2(gpu_gram(E).cpu().numpy())) / np.sqrt(herm_norm2(gpu_gram(A).cpu().numpy()))
-    assert loss < 1e-12, loss
-    assert res < 1e-12, res
-    # sampled check: S = V^T A (exact-arithmetic identity of eq. (4))
-    Sref = gpu_gram(V, A).cpu().numpy()
-    assert np.max(np.abs(S.cpu().numpy() - Sref)) < 1e-11
+    V, A = V.contiguous(), A.contiguous()
+    Qd, Rd, Sd = tho.two_stage(V, A)
+    Vh, Ah, Qg, Rg, Sg = to_host(V), to_host(A), to_host(Qd), to_host(Rd), to_host(Sd)
+    del V, A, Qd, Rd, Sd
+    torch.cuda.empty_cache()
+    Qo, Ro, So = oracle_two_stage(Vh, Ah)
+    tolj = _col_tol(Ro)
+    err = np.max(np.abs(Qg - Qo), axis=0)
+    print("max|dQ| %.2e (max err/tol %.3f), max|dR| %.2e, max|dS| %.2e"
+          % (err.max(), (err / tolj).max(), np.abs(Rg - Ro).max(), np.abs(Sg - So).max()), flush=True)
+    assert np.all(err <= tolj), (err / tolj).max()
+    assert np.abs(Rg - Ro).max() < 1e-10
+    assert np.abs(Sg - So).max() < 1e-10 * max(1.0, np.abs(So).max())
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+    vq, qq = orth_parts(Vh, Qg)
+    loss, res = orth_loss(Vh, Qg), rel_residual(Vh, Ah, Qg, Rg, Sg)
+    print("loss %.2e  ||V^TQ|| %.2e  ||Q^TQ-I|| %.2e  res %.2e" % (loss, vq, qq, res))
+    assert loss < 1e-12 and res < 1e-12
 
 
 @pytest.mark.parametrize("n,k0,k", [(1 << 18, 128, 64), (1 << 17, 128, 16), (1 << 17, 64, 64)])
@@ -181,3 +197,6 @@ def test_multi_tile_chunks(n, k0, k):
     assert rel_residual(V, A, Qg, Rg, Sg) < 1e-12
     assert np.abs(Sg - So).max() < 1e-10
     assert np.abs(Rg - Ro).max() < 1e-10
+    tolj = _col_tol(Ro)
+    err = np.max(np.abs(Qg - Qo), axis=0)
+    assert np.all(err <= tolj), (err / tolj).max()
