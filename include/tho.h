@@ -101,6 +101,28 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tho_two_stage without a workspace argument.  Its work buffer is a
+ * library-owned static device array of THO_NOALLOC_SCRATCH_BYTES bytes per
+ * GPU, held from the first call on that GPU until the process ends; the
+ * call allocates no device memory (hipMalloc, hipFree or any allocating
+ * library routine).  The first call on a device and host thread also
+ * creates that thread's side stream and two events (no device memory).
+ * Arguments 1-15 and the result are those of tho_two_stage (arguments 1-15)
+ * and its `stream` (argument 16); sizes whose tho_two_stage_workspace exceeds
+ * THO_NOALLOC_SCRATCH_BYTES are rejected with THO_E_WORKSPACE before any
+ * work is enqueued (for FP64 that admits, e.g., n = 2^20 with k0 = 64,
+ * k = 32).  Every call on one GPU shares that GPU's array and the array keeps
+ * the last call's contents (each call initialises what it reads):
+ * calls that overlap in time on the same GPU -- on different streams or from
+ * different host threads -- race and give wrong results; serialize them. */
+#define THO_NOALLOC_SCRATCH_BYTES (256u << 20)
+int tho_two_stage_noalloc(int32_t dtype, int64_t n, int64_t k0, int64_t k,
+                          const void* V, int64_t ldv, const void* A, int64_t lda,
+                          void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
+                          const tho_opts_t* opts, void* stream);
+
 /* Householder QR of the whole matrix [V, A] (the baseline the method is
  * compared with in §6: V's columns are factored too, nothing assumes V is
  * orthonormal).  Computed as the block Householder QR of Algorithm 4 over

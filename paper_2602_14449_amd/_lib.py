@@ -42,6 +42,11 @@ tho_two_stage = _proto(
     "tho_two_stage", ctypes.c_int,
     [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
      c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+tho_two_stage_noalloc = _proto(
+    "tho_two_stage_noalloc", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+     c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp])
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 tho_hhqr_full_workspace = _proto(
     "tho_hhqr_full_workspace", ctypes.c_int,
@@ -86,7 +91,7 @@ tho_batched_plan_info = _proto(
 tho_plan_destroy = _proto("tho_plan_destroy", ctypes.c_int, [c_vp])
 
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
-            "tho_two_stage_workspace", "tho_two_stage",
+            "tho_two_stage_workspace", "tho_two_stage", "tho_two_stage_noalloc",
             "tho_hhqr_full_workspace", "tho_hhqr_full",
             "tho_bcgs_workspace", "tho_bcgs",
             "tho_two_stage_backward_workspace", "tho_two_stage_backward",
