@@ -17,7 +17,12 @@ Modules
   householder  column Householder QR (the intra-block QR of
                Algorithm 1 and the QR of the top block for the second choice
                of P), with the nonnegative-diagonal phase convention
-  two_stage    Algorithm 1 with the second choice of P (§3.1, §3.2)
+  choices      the three choices of P and the factored T they give (§3.2:
+               modified LU of Algorithm 2, QR, polar decomposition)
+  two_stage    the two-stage method from the definitions of §3.1 (eq. (3),
+               eq. (4)), any choice of P
+  appendix_a   the matrix U of eq. (6) and the Appendix A construction of an
+               orthonormal V whose modified LU returns it (Example 4)
   baselines    Householder QR of [V, A] (start of §3) and the BCGS framework
                with reorthogonalization patterns (eq. (1), Table 1)
   metrics      loss of orthogonality and residual as printed in Tables 1-4
@@ -33,6 +38,8 @@ oracle).
 
 from .householder import householder_qr, qr_pos, phase_normalize  # noqa: F401
 from .two_stage import two_stage, two_stage_intermediates  # noqa: F401
+from .choices import choose_p, modified_lu, polar  # noqa: F401
+from .appendix_a import badmlu_u, badmlu_v  # noqa: F401
 from .baselines import hhqr_full, bcgs  # noqa: F401
 from .metrics import (  # noqa: F401
     orth_loss, orth_parts, rel_residual, gram_chunked, spectral_norm_tall)

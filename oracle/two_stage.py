@@ -1,32 +1,35 @@
-"""Algorithm 1 (two-stage Householder-QR) with the second choice of P (oracle).
+"""Two-stage Householder orthogonalization (oracle), written from the
+definitions of §3.1 and the choices of P of §3.2.
 
 Test infrastructure only (see ``oracle/__init__``).
 
-Followed passages
-  * §3.1: generalized Householder transformation H = I - W T^{-1} W^* with
-    X = [P; 0], Y = V, W = X - Y, T = W^* X (eq. (3)); stage two forms
-    H^* A, QRs its bottom n - k0 rows and sets Q = H [0; Q_], giving eq. (4):
-    [V, A] = [V, Q] [[I, S], [0, R]].
-  * Algorithm 1, steps in order: choose unitary P; W = [P; 0] - V;
-    T = I - V_top^* P; A <- (I - W T^{-*} W^*) A; S = P^* A_top;
-    QR of A_low = Q_ R; Q = (I - W T^{-1} W^*) [0; Q_].
-  * §3.2, second choice: V_top = Q1 R1 with nonnegative diag(R1), P = -Q1,
-    T = I + R1^* (lower triangular).  Appendix B.2 analyses exactly the
-    computed form T = fl(I + R1^*), which is the form used here.  (Algorithm 1 itself
-    writes T = I - V_top^* P, equal whenever Q1 is unitary; the
-    tests check the two agree to rounding.)
+Definitions followed
+  * §3.1, eq. (3): for X, Y with X^* X = Y^* Y, W = X - Y and T = W^* X
+    nonsingular, H = I - W T^{-1} W^* is unitary with H X = Y.  Here
+    X = [P; 0] for a unitary k0 x k0 matrix P and Y = V, so H = [V P^*, V_perp]
+    and H [P; 0] = V.
+  * Stage one applies H^* = I - W T^{-*} W^* to A: the top k0 rows of H^* A
+    are P V^* A, the bottom n - k0 rows are V_perp^* A.  Hence S = V^* A is
+    P^* times the top block.
+  * Stage two QR-factors the bottom block, V_perp^* A = Q_ R, and sets
+    Q = H [0; Q_]; then [V, A] = [V, Q] [[I, S], [0, R]] (eq. (4)).
+  * P and the factored T come from ``choices.choose_p`` (first choice:
+    modified LU; second: QR of V_top, the default and the paper's
+    recommendation; third: polar decomposition).  For the second choice
+    T = I + R1^* is the form analysed in Appendix B.2; it equals
+    I - V_top^* P whenever Q1 is unitary (tested).
 
 Readings taken where the paper is silent (listed in the design doc as well)
   * Intra-block QR: column Householder with the nonnegative-diagonal phase
     convention (``householder.qr_pos``).
-  * S is computed exactly as Algorithm 1 states, P^* A_top after the update, not
-    as V^* A (they agree in exact arithmetic when V^* V = I).
+  * S is computed as P^* times the top block of H^* A (as in the method's
+    statement), not as V^* A (they agree in exact arithmetic when V^* V = I).
   * n >= k0 + k is required; k0 = 0 reduces to qr_pos(A); k = 0 is a no-op.
 """
 
 import numpy as np
-from scipy.linalg import solve_triangular
 
+from .choices import choose_p
 from .householder import qr_pos
 
 
@@ -34,11 +37,26 @@ def _h(M):
     return np.conj(M).T
 
 
-def two_stage_intermediates(V, A, qr_method="auto"):
-    """Run Algorithm 1 (second choice of P) and return every intermediate.
+def apply_h_adjoint(Wm, Tf, B):
+    """H^* B = B - W T^{-*} (W^* B).  Returns (H^* B, W^* B, T^{-*} W^* B)."""
+    Y = _h(Wm) @ B
+    Z = Tf.solve_h(Y)
+    return B - Wm @ Z, Y, Z
 
-    Returns a dict with P, T, W, Y (= W^* A), Z (= T^{-*} Y), A1 (updated A),
-    S, Qu (Q_ of the bottom-block QR), R, G (= W^* [0; Q_]), N (= T^{-1} G) and Q.
+
+def apply_h(Wm, Tf, B):
+    """H B = B - W T^{-1} (W^* B).  Returns (H B, W^* B, T^{-1} W^* B)."""
+    G = _h(Wm) @ B
+    N = Tf.solve(G)
+    return B - Wm @ N, G, N
+
+
+def two_stage_intermediates(V, A, qr_method="auto", p_choice="qr"):
+    """Run the two-stage method and return every intermediate.
+
+    Returns a dict with P, T (explicit), Tf (factored T), W, Y (= W^* A),
+    Z (= T^{-*} Y), A1 (= H^* A), S, Qu (Q_ of the bottom-block QR), R,
+    G (= W^* [0; Q_]), N (= T^{-1} G) and Q; for the second choice also R1.
     """
     V = np.asarray(V)
     A = np.asarray(A)
@@ -51,50 +69,31 @@ def two_stage_intermediates(V, A, qr_method="auto"):
         raise ValueError("V and A must have the same number of rows")
     if n < k0 + k:
         raise ValueError("need n >= k0 + k")
-    out = {}
-    # choice of P, second choice (§3.2): V_top = Q1 R1, diag(R1) >= 0, P = -Q1
-    if k0 > 0:
-        Q1, R1 = qr_pos(V[:k0, :], method="loop")
-    else:
-        Q1 = np.zeros((0, 0), dt)
-        R1 = np.zeros((0, 0), dt)
-    P = -Q1
-    # W = [P; 0] - V
-    X0 = np.zeros((n, k0), dt)
-    X0[:k0, :] = P
-    W = X0 - V
-    # T in the form analysed in Appendix B.2: T = I + R1^* (lower tri.)
-    T = np.eye(k0, dtype=dt) + _h(R1)
-    # update of A: A <- A - W T^{-*} (W^* A)
-    Y = _h(W) @ A
-    if k0 > 0:
-        Z = solve_triangular(_h(T), Y, lower=False)   # T^* is upper triangular
-    else:
-        Z = np.zeros((0, k), dt)
-    A1 = A - W @ Z
-    # S = P^* A_top
+    # the generalized Householder transformation mapping [P; 0] onto V
+    P, Tf = choose_p(V[:k0, :], p_choice)
+    X = np.zeros((n, k0), dt)
+    X[:k0, :] = P
+    Wm = X - V
+    # stage one: H^* A = [P V^* A; V_perp^* A]
+    A1, Y, Z = apply_h_adjoint(Wm, Tf, A)
     S = _h(P) @ A1[:k0, :]
-    # QR of the bottom n - k0 rows
+    # QR of V_perp^* A
     if k > 0:
         Qu, R = qr_pos(A1[k0:, :], method=qr_method)
     else:
         Qu = np.zeros((n - k0, 0), dt)
         R = np.zeros((0, 0), dt)
-    # formation of Q: Q = [0; Q_] - W T^{-1} (W^* [0; Q_])
+    # stage two: Q = H [0; Q_]
     Xq = np.zeros((n, k), dt)
     Xq[k0:, :] = Qu
-    G = _h(W) @ Xq
-    if k0 > 0:
-        N = solve_triangular(T, G, lower=True)
-    else:
-        N = np.zeros((0, k), dt)
-    Q = Xq - W @ N
-    out.update(P=P, R1=R1, T=T, W=W, Y=Y, Z=Z, A1=A1, S=S, Qu=Qu, R=R, G=G,
-               N=N, Q=Q)
+    Q, G, N = apply_h(Wm, Tf, Xq)
+    out = dict(P=P, T=Tf.T, Tf=Tf, W=Wm, Y=Y, Z=Z, A1=A1, S=S, Qu=Qu, R=R,
+               G=G, N=N, Q=Q)
+    out.update(Tf.parts)
     return out
 
 
-def two_stage(V, A, qr_method="auto"):
-    """Algorithm 1 with the second choice of P.  Returns (Q, R, S)."""
-    o = two_stage_intermediates(V, A, qr_method=qr_method)
+def two_stage(V, A, qr_method="auto", p_choice="qr"):
+    """The two-stage method; returns (Q, R, S)."""
+    o = two_stage_intermediates(V, A, qr_method=qr_method, p_choice=p_choice)
     return o["Q"], o["R"], o["S"]
