@@ -127,23 +127,30 @@ def threads_used():
 
 
 def time_steps(fn, steps, warmup, stream):
+    """Headline time: `steps` calls bracketed by events on `stream`, with the
+    library's per-kernel event recording off.  The per-kernel breakdown then
+    comes from a separate run of the same number of steps with recording on
+    (its totals are per-kernel sums; they are divided by `steps` below)."""
     import torch
     from paper_2602_14449_amd import _lib
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    _lib.tho_profile_reset()
-    _lib.tho_profile_enable(1)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
         fn()
     e1.record(stream)
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    _lib.tho_profile_reset()
+    _lib.tho_profile_enable(1)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
     _lib.tho_profile_enable(0)
-    return e0.elapsed_time(e1) / steps, _lib.profile_read()
+    return ms, _lib.profile_read()
 
 
 def roofline(prof, model_fn, bound):
@@ -252,6 +259,8 @@ def compare(a, V, A, Q, R, S, stream):
     cands = [("hhqr_full", lambda: tho.hhqr_full(V, A, out=(Q, R, S))),
              ("bcgs_1_1", lambda: tho.bcgs(V, A, 1, 1, out=(Q, R, S))),
              ("bcgs_1_2", lambda: tho.bcgs(V, A, 1, 2, out=(Q, R, S))),
+             ("two_stage_p_mlu", lambda: tho.two_stage(V, A, p_choice="mlu", out=(Q, R, S))),
+             ("two_stage_p_polar", lambda: tho.two_stage(V, A, p_choice="polar", out=(Q, R, S))),
              ("two_stage_f32x2", lambda: tho.two_stage(V, A, panel="f32x2", out=(Q, R, S))),
              ("two_stage_bf16", lambda: tho.two_stage(V, A, panel="bf16", out=(Q, R, S)))]
     for name, fn in cands:

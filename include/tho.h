@@ -26,11 +26,14 @@
  *     workspace is caller-provided).  Calls with distinct workspaces may run
  *     concurrently.
  *   - Return value: 0 on success; -i when argument i (1-based) is invalid
- *     (LAPACK style: sizes, ld too small, NULL pointer, bad alignment);
+ *     (LAPACK style: sizes, ld too small, NULL pointer, bad alignment, an
+ *     output sharing elements with an input or another output);
  *     THO_E_WORKSPACE when ws_bytes is too small; THO_E_HIP when a HIP call
  *     failed (see tho_last_error()); THO_E_UNSUPPORTED for a valid but
- *     unimplemented combination.  Numerical conditions (non-finite input)
- *     are not errors of the call; they propagate as NaN like LAPACK.
+ *     unimplemented combination.  Numerical conditions (non-finite input,
+ *     a V that is not orthonormal) are not errors of the call: non-finite
+ *     values propagate as NaN like LAPACK, and tho_two_stage reports them
+ *     on request through a device info word (THO_CHECK_*, tho_get_info).
  */
 #ifndef THO_H
 #define THO_H
@@ -44,10 +47,23 @@ extern "C" {
 
 typedef enum { THO_F64 = 0, THO_C128 = 1 } tho_dtype_t;
 
-/* Choice of the unitary P of Algorithm 1 (§3.2).  Only the second
- * choice (QR of the top block, P = -Q1, T = I + R1^*) is implemented; it is
- * the one the paper recommends (§6.2, §7). */
-typedef enum { THO_P_QR = 0 } tho_pchoice_t;
+/* Choice of the unitary P of Algorithm 1 (§3.2), for the top k0 x k0 block
+ * V_top of V:
+ *   THO_P_QR     second choice (default; recommended in §6.2 and §7):
+ *                V_top = Q1 R1, diag(R1) >= 0, P = -Q1, T = I + R1^* (lower
+ *                triangular, kappa_2(T) < 2 sqrt(2) k0)
+ *   THO_P_MLU    first choice: P diagonal (+-1), fixed during the modified
+ *                LU factorization P - V_top = L U of Algorithm 2 [BDGJKN2015];
+ *                T = U^* L^* P.  Not always stable: kappa_2(U) can be large
+ *                (eq. (6), Table 4) and the loss of orthogonality grows with it
+ *   THO_P_POLAR  third choice: polar decomposition V_top = Q2 M, P = -Q2,
+ *                T = I + M (Hermitian positive definite, kappa_2(T) <= 2),
+ *                solved by Cholesky; the polar factor comes from a one-sided
+ *                Jacobi SVD of V_top in one workgroup
+ * Each runs in one workgroup beside the first reduction over n rows.  The
+ * complex path, the adjoint, the batched path, tho_hhqr_full and tho_bcgs use
+ * THO_P_QR only (THO_E_UNSUPPORTED otherwise). */
+typedef enum { THO_P_QR = 0, THO_P_MLU = 1, THO_P_POLAR = 2 } tho_pchoice_t;
 
 /* Arithmetic of the four n x k0 x k panel products of Algorithm 1 (V^*A,
  * the update A + V Z, V^*Q_ and Q_ + V N).  Reflector generation, norms and
@@ -58,10 +74,37 @@ typedef enum { THO_P_QR = 0 } tho_pchoice_t;
  * orthogonality of Q (about 1e-7 and 1e-3 respectively) for speed. */
 typedef enum { THO_PANEL_F64 = 0, THO_PANEL_F32X2 = 1, THO_PANEL_BF16 = 2 } tho_panel_t;
 
+/* Optional numerical-condition checks of tho_two_stage (opts->flags, OR of):
+ *   THO_CHECK_FINITE  report a non-finite value in V or A (or produced by
+ *                     overflow inside the method).  Costs one tiny kernel:
+ *                     every element of V and A is a factor in the
+ *                     reductions that form S and R (V^* A, the Householder
+ *                     column norms), and IEEE products and sums keep NaN and
+ *                     infinities non-finite (0 * Inf = NaN), so the check
+ *                     scans the k0 x k + k x k outputs S and R.
+ *   THO_CHECK_VORTH   report ||V^* V - I||_F > THO_VORTH_TOL (V is assumed
+ *                     orthonormal, Algorithm 1's precondition; the loss of
+ *                     orthogonality of Q grows with this distance, Theorem 1
+ *                     and the remark after it).  Costs one extra split-n
+ *                     Gram reduction over V (one more pass over V and
+ *                     2 n k0^2 flops).
+ * Results go to the info word (see tho_get_info), never to the return value:
+ * the call still completes and the outputs are written. */
+#define THO_CHECK_FINITE 1
+#define THO_CHECK_VORTH  2
+#define THO_VORTH_TOL    1e-10
+
+/* Codes of the info word (0 = no condition detected).  When several
+ * conditions hold, the smallest code is reported. */
+#define THO_INFO_NONFINITE        1
+#define THO_INFO_T_SINGULAR       2  /* reserved: no choice of P can give a singular T
+                                        (the modified-LU pivots have modulus >= 1) */
+#define THO_INFO_V_NOT_ORTHONORMAL 3
+
 typedef struct {
     int32_t p_choice;   /* tho_pchoice_t */
     int32_t panel;      /* tho_panel_t   */
-    int32_t flags;      /* reserved, must be 0 */
+    int32_t flags;      /* THO_CHECK_* bits (tho_two_stage, tho_two_stage_noalloc); 0 elsewhere */
     int32_t reserved;
 } tho_opts_t;
 
@@ -79,14 +122,19 @@ typedef struct {
 #define THO_MAX_K_C128  32
 
 /* Bytes of device workspace tho_two_stage needs for these sizes (opts may be
- * NULL for defaults).  Returns 0 or -i like the other calls. */
+ * NULL for defaults; p_choice and flags change the size).  Returns 0 or -i
+ * like the other calls.  The first 256 bytes of the workspace hold the info
+ * word of the last tho_two_stage call that used it (tho_get_info). */
 int tho_two_stage_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                             const tho_opts_t* opts, size_t* bytes);
 
-/* Algorithm 1 of the paper (§3.1) with the second choice of P (§3.2):
+/* Algorithm 1 of the paper (§3.1) with the choice of P in opts->p_choice
+ * (§3.2; default the second choice):
  *   P = -Q1 where V_top = Q1 R1 (diag R1 >= 0), W = [P; 0] - V, T = I + R1^*,
  *   A <- (I - W T^{-*} W^*) A,  S = P^* A_top,  A_low = Q_ R (Householder),
  *   Q = (I - W T^{-1} W^*) [0; Q_].
+ * In exact arithmetic (Q, R, S) do not depend on the choice of P; in
+ * floating point the first choice can lose orthogonality (Table 4).
  * Arguments: 1 dtype, 2 n, 3 k0, 4 k, 5 V (n x k0), 6 ldv, 7 A (n x k),
  * 8 lda, 9 Q (n x k, out), 10 ldq, 11 R (k x k, out), 12 ldr, 13 S (k0 x k,
  * out), 14 lds, 15 opts (NULL = defaults), 16 ws, 17 ws_bytes, 18 stream.
@@ -100,6 +148,17 @@ int tho_two_stage(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   const void* V, int64_t ldv, const void* A, int64_t lda,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* The info word of the last tho_two_stage call that used workspace `ws`
+ * (NULL: the calling device's static scratch of tho_two_stage_noalloc),
+ * as a THO_INFO_* code, 0 when no condition was detected or no check was
+ * requested.  Every tho_two_stage call with k > 0 rewrites the word on its
+ * stream; read it only after that stream has been synchronized (the call
+ * copies 4 bytes device to host with hipMemcpy).  Arguments: 1 ws (device),
+ * 2 host_info (host, out).  Returns 0, -2 for a NULL host_info, THO_E_HIP,
+ * or THO_E_UNSUPPORTED for ws = NULL before any tho_two_stage_noalloc call
+ * on the device. */
+int tho_get_info(const void* ws, int32_t* host_info);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -138,6 +197,44 @@ int tho_hhqr_full(int32_t dtype, int64_t n, int64_t k0, int64_t k,
                   const void* V, int64_t ldv, const void* A, int64_t lda,
                   void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
                   const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Block Householder-QR (Algorithm 4, §6.1): A = [A_1, ..., A_p] (n x K,
+ * block widths kb[0..p-1], each in [1, THO_MAX_K], K = sum of widths <= n)
+ * factored block by block as block Krylov methods produce the blocks:
+ * A = Q R with Q^* Q = I (n x K) and R upper triangular (K x K,
+ * nonnegative diagonal).  Block i is orthogonalized against the basis
+ * [Q_1, ..., Q_{i-1}] of the blocks before it by a generalized Householder
+ * transformation and its bottom rows are factored by Householder QR, so the
+ * basis may be far wider than THO_MAX_K0.  The transformation of block i
+ * uses the block-diagonal P = diag(P_1, ..., P_{i-1}), P_j by opts->p_choice
+ * from block j's own bottom basis, which makes it the product of one
+ * Algorithm 1 transformation per earlier block (each a pass over the rows
+ * below that block); Q and R do not depend on P in exact arithmetic.
+ * Real FP64 only.
+ * tho_block_householder: arguments 1 dtype, 2 n, 3 nblocks, 4 kb (host
+ * array), 5 A (n x K), 6 lda, 7 Q (n x K, out), 8 ldq, 9 R (K x K, out,
+ * strictly lower part written as 0), 10 ldr, 11 opts (panel and flags must
+ * be default), 12 ws, 13 ws_bytes, 14 stream.  Q and R must not overlap A
+ * or each other.
+ * tho_block_householder_step appends one block to a basis kept in the
+ * workspace (the append operation of a block Krylov loop): block i
+ * (0-based) with widths kb[0..i]; call it for i = 0, 1, 2, ... with the
+ * same Q, R and workspace.  Arguments 1 dtype, 2 n, 3 i, 4 kb, 5 kmax (the
+ * largest total width the workspace is sized for), 6 A_i (n x k_i), 7 lda,
+ * 8 Q (n x kmax: columns of earlier blocks as written by earlier steps;
+ * block i's columns are written), 9 ldq, 10 R (written: rows
+ * 0 .. c_i + k_i - 1 of block column i, c_i = kb[0] + ... + kb[i-1]),
+ * 11 ldr, 12 opts, 13 ws, 14 ws_bytes, 15 stream.
+ * tho_block_householder_workspace(dtype, n, kmax, opts, bytes) sizes the
+ * workspace of either call for total widths up to kmax (it holds the n x kmax
+ * bottom bases of the blocks).  Errors as elsewhere (-i, THO_E_*). */
+int tho_block_householder_workspace(int32_t dtype, int64_t n, int64_t kmax, const tho_opts_t* opts, size_t* bytes);
+int tho_block_householder(int32_t dtype, int64_t n, int32_t nblocks, const int64_t* kb, const void* A, int64_t lda,
+                          void* Q, int64_t ldq, void* R, int64_t ldr, const tho_opts_t* opts, void* ws,
+                          size_t ws_bytes, void* stream);
+int tho_block_householder_step(int32_t dtype, int64_t n, int32_t i, const int64_t* kb, int64_t kmax, const void* Ai,
+                               int64_t lda, void* Q, int64_t ldq, void* R, int64_t ldr, const tho_opts_t* opts,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* Block classical Gram-Schmidt, the baseline of eq. (1) and Table 1:
  * `rounds` rounds, each running `proj` projections

@@ -47,6 +47,22 @@ tho_two_stage_noalloc = _proto(
     [c_i32, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
      c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp])
 NOALLOC_SCRATCH_BYTES = 256 << 20
+tho_block_householder_workspace = _proto(
+    "tho_block_householder_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_block_householder = _proto(
+    "tho_block_householder", ctypes.c_int,
+    [c_i32, c_i64, c_i32, ctypes.POINTER(c_i64), c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+     ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+tho_block_householder_step = _proto(
+    "tho_block_householder_step", ctypes.c_int,
+    [c_i32, c_i64, c_i32, ctypes.POINTER(c_i64), c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+     ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+tho_get_info = _proto("tho_get_info", ctypes.c_int, [c_vp, ctypes.POINTER(c_i32)])
+CHECK_FINITE = 1
+CHECK_VORTH = 2
+INFO_NONFINITE = 1
+INFO_V_NOT_ORTHONORMAL = 3
 
 tho_hhqr_full_workspace = _proto(
     "tho_hhqr_full_workspace", ctypes.c_int,
@@ -91,7 +107,8 @@ tho_batched_plan_info = _proto(
 tho_plan_destroy = _proto("tho_plan_destroy", ctypes.c_int, [c_vp])
 
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
-            "tho_two_stage_workspace", "tho_two_stage", "tho_two_stage_noalloc",
+            "tho_two_stage_workspace", "tho_two_stage", "tho_two_stage_noalloc", "tho_get_info",
+            "tho_block_householder_workspace", "tho_block_householder", "tho_block_householder_step",
             "tho_hhqr_full_workspace", "tho_hhqr_full",
             "tho_bcgs_workspace", "tho_bcgs",
             "tho_two_stage_backward_workspace", "tho_two_stage_backward",
@@ -101,6 +118,7 @@ EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
 THO_F64 = 0
 THO_C128 = 1
 PANELS = {"fp64": 0, "f32x2": 1, "bf16": 2}
+PCHOICES = {"qr": 0, "mlu": 1, "polar": 2}
 
 
 class ThoError(RuntimeError):

@@ -7,11 +7,15 @@ import torch
 from . import _lib as L
 
 
-def _opts(panel="fp64"):
+def _opts(panel="fp64", p_choice="qr", check_finite=False, check_vorth=False):
     o = L.Opts()
-    o.p_choice = 0
+    if p_choice not in L.PCHOICES:
+        raise ValueError("p_choice must be one of %s" % sorted(L.PCHOICES))
+    if panel not in L.PANELS:
+        raise ValueError("panel must be one of %s" % sorted(L.PANELS))
+    o.p_choice = L.PCHOICES[p_choice]
     o.panel = L.PANELS[panel]
-    o.flags = 0
+    o.flags = (L.CHECK_FINITE if check_finite else 0) | (L.CHECK_VORTH if check_vorth else 0)
     return o
 
 
@@ -103,21 +107,27 @@ def _workspace(nbytes, workspace, dev):
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
 
 
-def workspace_bytes(n, k0, k, dtype=torch.float64, panel="fp64"):
+def workspace_bytes(n, k0, k, dtype=torch.float64, panel="fp64", p_choice="qr",
+                    check_finite=False, check_vorth=False):
     code = L.THO_F64 if dtype == torch.float64 else L.THO_C128
     nb = L.c_sz(0)
-    o = _opts(panel)
+    o = _opts(panel, p_choice, check_finite, check_vorth)
     L.check(L.tho_two_stage_workspace(code, n, k0, k, ctypes.byref(o), ctypes.byref(nb)),
             "tho_two_stage_workspace")
     return nb.value
 
 
-def two_stage(V, A, *, panel="fp64", out=None, workspace=None):
-    """Algorithm 1 (second choice of P): returns (Q, R, S) with
-    [V, A] = [V, Q] [[I, S], [0, R]] and [V, Q] orthonormal."""
+def two_stage(V, A, *, p_choice="qr", panel="fp64", check_finite=False, check_vorth=False,
+              out=None, workspace=None):
+    """Algorithm 1: returns (Q, R, S) with [V, A] = [V, Q] [[I, S], [0, R]]
+    and [V, Q] orthonormal.  p_choice: "qr" (second choice of P, default),
+    "mlu" (first choice, modified LU) or "polar" (third choice).
+    check_finite / check_vorth ask the library to record a non-finite input
+    or a V with ||V^T V - I||_F above 1e-10 in the workspace's info word; pass
+    your own ``workspace`` and read it with ``get_info(workspace)``."""
     code, n, k0, k = _check_inputs(V, A)
     Q, R, S = _outputs(out, n, k0, k, A)
-    o = _opts(panel)
+    o = _opts(panel, p_choice, check_finite, check_vorth)
     nb = L.c_sz(0)
     L.check(L.tho_two_stage_workspace(code, n, k0, k, ctypes.byref(o), ctypes.byref(nb)),
             "tho_two_stage_workspace")
@@ -130,6 +140,91 @@ def two_stage(V, A, *, panel="fp64", out=None, workspace=None):
                          _stream(A.device))
     L.check(rc, "tho_two_stage")
     return Q, R, S
+
+
+def block_householder(A, block_sizes, *, p_choice="qr", out=None, workspace=None):
+    """Algorithm 4 (block Householder-QR) of the column blocks of A (widths
+    ``block_sizes``, each <= 64): returns (Q, R) with A = Q R, Q^T Q = I, R
+    upper triangular with nonnegative diagonal."""
+    if not isinstance(A, torch.Tensor) or A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D GPU tensor")
+    if A.dtype != torch.float64:
+        raise TypeError("block_householder supports float64 only")
+    n, kt = A.shape
+    kb = [int(b) for b in block_sizes]
+    if sum(kb) != kt:
+        raise ValueError("block sizes must add up to the number of columns")
+    if out is not None:
+        Q, R = out
+        _check_out(Q, (n, kt), A, "out Q")
+        _check_out(R, (kt, kt), A, "out R")
+    else:
+        Q = torch.empty((n, kt), dtype=A.dtype, device=A.device)
+        R = torch.empty((kt, kt), dtype=A.dtype, device=A.device)
+    o = _opts("fp64", p_choice)
+    nb = L.c_sz(0)
+    L.check(L.tho_block_householder_workspace(L.THO_F64, n, kt, ctypes.byref(o), ctypes.byref(nb)),
+            "tho_block_householder_workspace")
+    workspace = _workspace(nb.value, workspace, A.device)
+    arr = (L.c_i64 * max(len(kb), 1))(*kb)
+    rc = L.tho_block_householder(L.THO_F64, n, len(kb), arr, A.data_ptr(), _ld(A, "A"), Q.data_ptr(), _ld(Q, "Q"),
+                                 R.data_ptr(), _ld(R, "R"), ctypes.byref(o), workspace.data_ptr(),
+                                 workspace.numel(), _stream(A.device))
+    L.check(rc, "tho_block_householder")
+    return Q, R
+
+
+class BlockHouseholder:
+    """Incremental Algorithm 4: ``append(A_i)`` orthogonalizes one more block
+    against the basis built so far and returns (Q_i, R_col_i), the new basis
+    columns and the rows 0 .. c_i + k_i - 1 of R's block column."""
+
+    def __init__(self, n, kmax, *, device="cuda", p_choice="qr"):
+        self.n, self.kmax = int(n), int(kmax)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.opts = _opts("fp64", p_choice)
+        nb = L.c_sz(0)
+        L.check(L.tho_block_householder_workspace(L.THO_F64, self.n, self.kmax, ctypes.byref(self.opts),
+                                                  ctypes.byref(nb)), "tho_block_householder_workspace")
+        self.ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=self.device)
+        self.Q = torch.zeros((self.n, self.kmax), dtype=torch.float64, device=self.device)
+        self.R = torch.zeros((self.kmax, self.kmax), dtype=torch.float64, device=self.device)
+        self.widths = []
+
+    @property
+    def ncols(self):
+        return sum(self.widths)
+
+    def append(self, Ai):
+        if Ai.dtype != torch.float64 or Ai.device != self.device or Ai.dim() != 2 or Ai.shape[0] != self.n:
+            raise ValueError("A_i must be a float64 (n, k_i) tensor on %s" % self.device)
+        c0, ki = self.ncols, Ai.shape[1]
+        if c0 + ki > self.kmax:
+            raise ValueError("basis would exceed kmax = %d columns" % self.kmax)
+        kb = self.widths + [ki]
+        arr = (L.c_i64 * len(kb))(*kb)
+        rc = L.tho_block_householder_step(L.THO_F64, self.n, len(kb) - 1, arr, self.kmax, Ai.data_ptr(),
+                                          _ld(Ai, "A_i"), self.Q.data_ptr(), self.kmax, self.R.data_ptr(),
+                                          self.kmax, ctypes.byref(self.opts), self.ws.data_ptr(), self.ws.numel(),
+                                          _stream(self.device))
+        L.check(rc, "tho_block_householder_step")
+        self.widths.append(ki)
+        return self.Q[:, c0:c0 + ki], self.R[:c0 + ki, c0:c0 + ki]
+
+
+def get_info(workspace=None):
+    """Info word of the last two_stage call on ``workspace`` (None: the
+    static scratch of the no-allocation entry point on the current device):
+    0, INFO_NONFINITE (1) or INFO_V_NOT_ORTHONORMAL (3).  Synchronizes the
+    current stream first."""
+    torch.cuda.current_stream().synchronize()
+    v = L.c_i32(0)
+    L.check(L.tho_get_info(workspace.data_ptr() if workspace is not None else None, ctypes.byref(v)),
+            "tho_get_info")
+    return v.value
 
 
 def hhqr_full(V, A, *, out=None, workspace=None):

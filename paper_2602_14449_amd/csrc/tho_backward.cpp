@@ -131,6 +131,20 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
     if (ldda < k) return set_err(-22, "ldda < k");
     for (const void* p : {gQ_, gR_, gS_, (const void*)dV_, (const void*)dA_})
         if (p && ((uintptr_t)p & 7)) return set_err(-13, "matrices must be 8-byte aligned");
+    {
+        // dV (arg 19) and dA (arg 21) must not share elements with an input or each other
+        struct Blk { const void* p; int64_t r, c, ld; };
+        const Blk in[] = {{V_, n, k0, ldv}, {A_, n, k, lda}, {Q_, n, k, ldq}, {R_, k, k, ldr},
+                          {gQ_, n, k, ldgq}, {gR_, k, k, ldgr}, {gS_, k0, k, ldgs}};
+        const Blk dv{dV_, n, k0, lddv}, da{dA_, n, k, ldda};
+        for (const Blk& b : in) {
+            if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, b.p, b.r, b.c, b.ld, 8))
+                return set_err(-19, "dV overlaps an input");
+            if (blocks_overlap(da.p, da.r, da.c, da.ld, b.p, b.r, b.c, b.ld, 8))
+                return set_err(-21, "dA overlaps an input");
+        }
+        if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, da.p, da.r, da.c, da.ld, 8)) return set_err(-21, "dA overlaps dV");
+    }
     if (!ws) return set_err(-24, "workspace is NULL");
     BwdPlan P;
     make_bwd_plan(n, k0, k, nullptr, P);

@@ -73,13 +73,15 @@ int tho_bcgs(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V_, in
              int32_t rounds, const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
-    if (opts && (opts->panel != THO_PANEL_F64 || opts->flags != 0))
+    if (opts && (opts->panel != THO_PANEL_F64 || opts->flags != 0 || opts->p_choice != THO_P_QR))
         return set_err(THO_E_UNSUPPORTED, "tho_bcgs supports panel=THO_PANEL_F64 only");
     if ((rc = check_pr(proj, rounds, 15, 16))) return rc;
     if (dtype == THO_C128 && !zsupported(k0, k))
         return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
     if (k == 0) return 0;
     if ((rc = check_io(k0, k, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds))) return rc;
+    if ((rc = check_alias(n, k0, k, dtype == THO_C128 ? 16 : 8, V_, ldv, A_, lda, Q_, ldq, R_, ldr, S_, lds)))
+        return rc;
     if (!ws) return set_err(-18, "workspace is NULL");
     if (dtype == THO_C128) {
         if (ws_bytes < zbcgs_bytes(n, k0, k)) return set_err(THO_E_WORKSPACE, "workspace too small");

@@ -22,6 +22,27 @@ int prof_collect();
 int prof_reset();
 int prof_get(int i, char* name, int name_len, double* total_ms, int64_t* launches);
 
+// Address of the calling device's static scratch of tho_two_stage_noalloc
+// (set up by its first call on the device; THO_E_UNSUPPORTED before that).
+int noalloc_scratch(const void** out);
+// Outputs Q, R, S (arguments 9, 11, 13) sharing elements with the inputs
+// or each other: -i.  esz = bytes per element.
+int check_alias(int64_t n, int64_t k0, int64_t k, int64_t esz, const void* V, int64_t ldv, const void* A,
+                int64_t lda, const void* Q, int64_t ldq, const void* R, int64_t ldr, const void* S, int64_t lds);
+bool blocks_overlap(const void* p1, int64_t r1, int64_t c1, int64_t ld1, const void* p2, int64_t r2, int64_t c2,
+                    int64_t ld2, int64_t esz);
+
+// P and T for the chosen P of §3.2 (k0 x k0 top block, ld k0 outputs) and
+// the solves with T^T and T that Algorithm 1 needs (tho_api.cpp).
+int p_and_t(int pchoice, int k0, const double* V, int64_t ldv, double* Pm, double* Tm, double* F2, double* pws,
+            hipStream_t s);
+int solve_tt(int pchoice, int k0, int k, const double* Tm, const double* F2, double* B, int64_t ldb, hipStream_t st);
+int solve_t(int pchoice, int k0, int k, const double* Tm, const double* F2, double* B, int64_t ldb, hipStream_t st);
+// Householder QR (nonnegative diag R) of an m x k block, k <= 64.
+size_t plain_qr_bytes(int64_t m, int64_t k);
+int run_plain_qr(int64_t m, int64_t k, const double* X, int64_t ldx, double* Q, int64_t ldq, double* R, int64_t ldr,
+                 void* ws, hipStream_t st);
+
 // dtype and size checks shared by the entry points (codes of arguments 1-4).
 int check_common(int32_t dtype, int64_t n, int64_t k0, int64_t k);
 // Pointer / leading-dimension checks of the (V, A, Q, R, S) argument block

@@ -63,6 +63,22 @@ hipError_t launch_small_gemm(int M, int N, int K, double alpha, const double* A,
 hipError_t launch_trsm_lower(int n, int m, const double* L, int64_t ldl, int trans, double* B,
                              int64_t ldb, hipStream_t st);
 hipError_t launch_qr_top(int n, const double* Vt, int64_t ldv, double* P, double* T, hipStream_t st);
+// First and third choices of P for the n x n top block (n <= 128), one
+// workgroup each (k_pchoice.hip).  launch_mlu_top: P = diag, F1 = P L,
+// F2 = U^T with P - V_top = L U (Algorithm 2).  launch_polar_top: P = -Q2
+// and C = chol(I + M) for V_top = Q2 M; ws holds pchoice_ws_doubles(n).
+hipError_t launch_mlu_top(int n, const double* Vt, int64_t ldv, double* P, double* F1, double* F2, hipStream_t st);
+hipError_t launch_polar_top(int n, const double* Vt, int64_t ldv, double* P, double* C, double* ws, hipStream_t st);
+size_t pchoice_ws_doubles(int n);
+
+// Numerical-condition checks (k_checks.hip): the info word is INT_MAX until
+// a condition lowers it (atomicMin) to its code.
+hipError_t launch_info_reset(int* info, hipStream_t st);
+hipError_t launch_check_finite(int k0, int k, int cplx, const double* S, int64_t lds, const double* R, int64_t ldr,
+                               int* info, hipStream_t st);
+// G0, G1: column blocks 0..63 and 64.. of the Gram (ld ld0, ld1).
+hipError_t launch_vorth_check(int k0, int cplx, const double* G0, int ld0, const double* G1, int ld1, double tol,
+                              int* info, hipStream_t st);
 hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
                            double* G0, hipStream_t st);
 hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st);

@@ -45,6 +45,16 @@ int scratch_for_current_device(void** out) {
 
 }  // namespace
 
+int tho::noalloc_scratch(const void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= kMaxDevices || !g_ptr[dev])
+        return tho::set_err(THO_E_UNSUPPORTED, "tho_two_stage_noalloc has not run on this device");
+    *out = g_ptr[dev];
+    return 0;
+}
+
 extern "C" int tho_two_stage_noalloc(int32_t dtype, int64_t n, int64_t k0, int64_t k, const void* V, int64_t ldv,
                                      const void* A, int64_t lda, void* Q, int64_t ldq, void* R, int64_t ldr,
                                      void* S, int64_t lds, const tho_opts_t* opts, void* stream) {
