@@ -114,8 +114,8 @@ typedef struct {
 
 /* Largest supported k0 and k (the k0 x k0 and k x k factorizations run
  * inside one workgroup).  THO_C128 supports k0 <= 64 and k <= 32
- * (THO_E_UNSUPPORTED beyond); reduced-precision panels, the adjoint and the
- * batched path are real (THO_F64) only. */
+ * (THO_E_UNSUPPORTED beyond); reduced-precision panels and the batched
+ * path are real (THO_F64) only. */
 #define THO_MAX_K0 128
 #define THO_MAX_K  64
 #define THO_MAX_K0_C128 64
@@ -258,7 +258,8 @@ int tho_bcgs(int32_t dtype, int64_t n, int64_t k0, int64_t k,
              const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint (reverse-mode gradient) of the map (V, A) -> (Q, R, S) that
- * tho_two_stage computes, real FP64.  The paper does not treat
+ * tho_two_stage computes, real FP64 and complex128 (k0 <= 64, k <= 32 for
+ * complex).  The paper does not treat
  * differentiation; this is the exact adjoint of the steps of Algorithm 1
  * (second choice of P) taken in reverse order, with the thin-QR adjoint
  * X_bar = (Q_bar + Q copyltu(R R_bar^T - Q_bar^T Q)) R^{-T} for the QR of
@@ -267,8 +268,12 @@ int tho_bcgs(int32_t dtype, int64_t n, int64_t k0, int64_t k,
  * it returns dV = dl/dV and dA = dl/dA, V and A taken as unconstrained
  * matrices.  Q and R must be the outputs of tho_two_stage for (V, A); the
  * WY factors are recomputed from V, A, Q (never stored), using W^T Q = -T^T N
- * which holds for orthonormal V.
- * Arguments: 1 dtype (THO_F64), 2 n, 3 k0, 4 k, 5 V, 6 ldv, 7 A, 8 lda,
+ * which holds for orthonormal V.  Complex data: the loss is
+ * l = Re<gQ, Q> + Re<gR, R> + Re<gS, S> with <X, Y> = sum conj(X) Y, and dV,
+ * dA satisfy dl = Re<dV, dV_dir> + Re<dA, dA_dir> (PyTorch's convention);
+ * the steps are the same with conjugate transposes, and the thin-QR adjoint
+ * uses copyltu(M) = tril(M, -1) + tril(M, -1)^H + Re(diag M).
+ * Arguments: 1 dtype, 2 n, 3 k0, 4 k, 5 V, 6 ldv, 7 A, 8 lda,
  * 9 Q, 10 ldq, 11 R, 12 ldr, 13 gQ (n x k), 14 ldgq, 15 gR (k x k),
  * 16 ldgr, 17 gS (k0 x k, may be NULL for zero), 18 ldgs, 19 dV (n x k0,
  * out), 20 lddv, 21 dA (n x k, out), 22 ldda, 23 opts, 24 ws, 25 ws_bytes,

@@ -277,7 +277,9 @@ def bcgs(V, A, proj=1, rounds=1, *, out=None, workspace=None):
 
 def two_stage_backward(V, A, Q, R, gQ, gR, gS=None, *, workspace=None):
     """Adjoint of (V, A) -> (Q, R, S): returns (dV, dA) for the loss
-    gradients gQ = dl/dQ, gR = dl/dR (upper triangle used), gS = dl/dS."""
+    gradients gQ = dl/dQ, gR = dl/dR (upper triangle used), gS = dl/dS.
+    Complex data: dl = Re<dV, dV_dir> + Re<dA, dA_dir> with <X, Y> =
+    sum conj(X) Y, for l = Re<gQ, Q> + Re<gR, R> + Re<gS, S>."""
     code, n, k0, k = _check_inputs(V, A)
     _check_out(Q, (n, k), A, "Q")
     _check_out(R, (k, k), A, "R")
@@ -406,7 +408,8 @@ class TwoStageFunction(torch.autograd.Function):
 
 
 def two_stage_autograd(V, A):
-    """Differentiable two_stage (real float64)."""
-    if V.dtype != torch.float64 or A.dtype != torch.float64:
-        raise TypeError("the adjoint is implemented for float64 only")
+    """Differentiable two_stage (float64 or complex128; for complex data the
+    gradients follow PyTorch's convention for real losses)."""
+    if V.dtype != A.dtype or A.dtype not in (torch.float64, torch.complex128):
+        raise TypeError("the adjoint is implemented for float64 and complex128")
     return TwoStageFunction.apply(V, A)

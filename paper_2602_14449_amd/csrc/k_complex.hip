@@ -445,6 +445,31 @@ __global__ void k_zcombine(int p, int q, const double* Cr, int64_t ldc, double s
     out[(int64_t)i * ldo + j] = cmk(sign * (rr + ii), sign * (ri - ir));
 }
 
+// D = a op(X) + b op(Y) + c I (complex M x N; real a, b, c; op 0 none,
+// 1 transpose, 2 conjugate transpose; X or Y may be NULL), masked: mode 1
+// keeps j <= i, mode 2 keeps j >= i, mode 3 is copyltu for complex data
+// (D_ij for i > j, conj(D_ji) above the diagonal, Re(D_ii) on it).
+__global__ void k_zsmall_ew(int M, int N, double a, const cplx* X, int64_t ldx, int opx, double b, const cplx* Y,
+                            int64_t ldy, int opy, double c, int mode, cplx* D, int64_t ldd) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * N) return;
+    const int i = (int)(t / N), j = (int)(t % N);
+    const bool mirror = (mode == 3 && j > i);
+    const int si = mirror ? j : i, sj = mirror ? i : j;
+    auto at = [&](const cplx* P, int64_t ld, int op) {
+        const cplx v = op ? P[(int64_t)sj * ld + si] : P[(int64_t)si * ld + sj];
+        return (op == 2) ? cconj(v) : v;
+    };
+    cplx v = cmk(0.0, 0.0);
+    if (X) v = cadd(v, cscale(at(X, ldx, opx), a));
+    if (Y) v = cadd(v, cscale(at(Y, ldy, opy), b));
+    if (si == sj) v.re += c;
+    if (mirror) v = cconj(v);
+    if (mode == 3 && i == j) v.im = 0.0;
+    if ((mode == 1 && j > i) || (mode == 2 && j < i)) v = cmk(0.0, 0.0);
+    D[(int64_t)i * ldd + j] = v;
+}
+
 // Real 2 x 2 block form of a p x q complex B (ld ldb), scaled by sign:
 // dst (2p x 2q, ld 2q) with rows (2i, 2i+1), columns (2j, 2j+1) =
 // [[br, bi], [-bi, br]], so that [yr, yi] dst-block = [re, im] of y b.
@@ -584,6 +609,15 @@ hipError_t launch_zfinish_r(int k, int KP, const void* Rin, int64_t ldri, void* 
                             hipStream_t st) {
     hipLaunchKernelGGL(k_zfinish_r, dim3(1), dim3(256), 0, st, k, KP, (const cplx*)Rin, ldri, (cplx*)Rout, ldr,
                        (cplx*)G0);
+    return hipGetLastError();
+}
+
+hipError_t launch_zsmall_ew(int M, int N, double a, const void* X, int64_t ldx, int opx, double b, const void* Y,
+                            int64_t ldy, int opy, double c, int mode, void* D, int64_t ldd, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t nb = ((int64_t)M * N + 255) / 256;
+    hipLaunchKernelGGL(k_zsmall_ew, dim3((unsigned)nb), dim3(256), 0, st, M, N, a, (const cplx*)X, ldx, opx, b,
+                       (const cplx*)Y, ldy, opy, c, mode, (cplx*)D, ldd);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // Reverse-mode adjoint of the map (V, A) -> (Q, R, S) computed by
-// tho_two_stage (Algorithm 1, second choice of P), real FP64.
+// tho_two_stage (Algorithm 1, second choice of P), real FP64 (the complex128
+// adjoint, the same steps with conjugate transposes, is in tho_complex.cpp).
 //
 // The paper does not treat differentiation; this is the exact adjoint of the
 // forward steps, taken in reverse order:
@@ -102,6 +103,11 @@ int tho_two_stage_backward_workspace(int32_t dtype, int64_t n, int64_t k0, int64
     if (!bytes) return set_err(-6, "bytes must not be NULL");
     (void)opts;
     if (k == 0) { *bytes = 0; return 0; }
+    if (dtype == THO_C128) {
+        if (!zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
+        *bytes = ztwo_stage_backward_bytes(n, k0, k);
+        return 0;
+    }
     BwdPlan P;
     make_bwd_plan(n, k0, k, nullptr, P);
     *bytes = P.bytes;
@@ -115,7 +121,9 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
                            void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(dtype, n, k0, k);
     if (rc) return rc;
-    if (dtype != THO_F64) return set_err(THO_E_UNSUPPORTED, "the adjoint is implemented for THO_F64 only");
+    const bool cplx = dtype == THO_C128;
+    const int64_t esz = cplx ? 16 : 8;
+    if (cplx && !zsupported(k0, k)) return set_err(THO_E_UNSUPPORTED, "complex128 supports k0 <= 64, k <= 32");
     if (opts && (opts->p_choice != THO_P_QR || opts->panel != THO_PANEL_F64 || opts->flags != 0))
         return set_err(THO_E_UNSUPPORTED, "the adjoint supports p_choice=THO_P_QR, panel=THO_PANEL_F64 only");
     if (k == 0) return 0;
@@ -129,8 +137,8 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
     if (k0 > 0 && lddv < k0) return set_err(-20, "lddv < k0");
     if (!dA_) return set_err(-21, "dA is NULL");
     if (ldda < k) return set_err(-22, "ldda < k");
-    for (const void* p : {gQ_, gR_, gS_, (const void*)dV_, (const void*)dA_})
-        if (p && ((uintptr_t)p & 7)) return set_err(-13, "matrices must be 8-byte aligned");
+    for (const void* p : {V_, A_, Q_, R_, gQ_, gR_, gS_, (const void*)dV_, (const void*)dA_})
+        if (p && ((uintptr_t)p & (esz - 1))) return set_err(-13, "matrices must be aligned to their element size");
     {
         // dV (arg 19) and dA (arg 21) must not share elements with an input or each other
         struct Blk { const void* p; int64_t r, c, ld; };
@@ -138,14 +146,22 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
                           {gQ_, n, k, ldgq}, {gR_, k, k, ldgr}, {gS_, k0, k, ldgs}};
         const Blk dv{dV_, n, k0, lddv}, da{dA_, n, k, ldda};
         for (const Blk& b : in) {
-            if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, b.p, b.r, b.c, b.ld, 8))
+            if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, b.p, b.r, b.c, b.ld, esz))
                 return set_err(-19, "dV overlaps an input");
-            if (blocks_overlap(da.p, da.r, da.c, da.ld, b.p, b.r, b.c, b.ld, 8))
+            if (blocks_overlap(da.p, da.r, da.c, da.ld, b.p, b.r, b.c, b.ld, esz))
                 return set_err(-21, "dA overlaps an input");
         }
-        if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, da.p, da.r, da.c, da.ld, 8)) return set_err(-21, "dA overlaps dV");
+        if (blocks_overlap(dv.p, dv.r, dv.c, dv.ld, da.p, da.r, da.c, da.ld, esz))
+            return set_err(-21, "dA overlaps dV");
     }
     if (!ws) return set_err(-24, "workspace is NULL");
+    if (cplx) {
+        if (ws_bytes < ztwo_stage_backward_bytes(n, k0, k)) return set_err(THO_E_WORKSPACE, "workspace too small");
+        return run_ztwo_stage_backward(n, k0, k, (const dcplx*)V_, ldv, (const dcplx*)A_, lda, (const dcplx*)Q_, ldq,
+                                       (const dcplx*)R_, ldr, (const dcplx*)gQ_, ldgq, (const dcplx*)gR_, ldgr,
+                                       (const dcplx*)gS_, ldgs, (dcplx*)dV_, lddv, (dcplx*)dA_, ldda, ws,
+                                       (hipStream_t)stream);
+    }
     BwdPlan P;
     make_bwd_plan(n, k0, k, nullptr, P);
     if (ws_bytes < P.bytes) return set_err(THO_E_WORKSPACE, "workspace too small");

@@ -343,3 +343,211 @@ int run_zhhqr(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, con
 }
 
 }  // namespace tho
+
+// ---- adjoint of (V, A) -> (Q, R, S) for complex128 (second choice of P).
+// The steps of the real adjoint (tho_backward.cpp) with conjugate
+// transposes; gradients follow dl = Re<V_bar, dV> + Re<A_bar, dA>,
+// <X, Y> = sum conj(X) Y, for l = Re<G_Q, Q> + Re<G_R, R> + Re<G_S, S>.  The
+// thin-QR adjoint of X = Q R (real positive diag R) is
+//   X_bar = (Q_bar + Q copyltu(M)) R^{-H},  M = R R_bar^H - Q_bar^H Q,
+// copyltu(M) = tril(M, -1) + tril(M, -1)^H + Re(diag M).
+namespace {
+
+// Out (nrows x q) = X + sum_t sign_t Y_t B_t, complex, one row-streaming pass.
+struct ZRowsN {
+    static constexpr int MAXT = 3;
+    double *exp[MAXT], *pk[MAXT];
+};
+struct ZTerm {
+    const dcplx* Y;
+    int64_t ldy;
+    int p;
+    const dcplx* B;
+    int64_t ldb;
+    double sign;
+};
+
+void zrowsn_plan(int pmax, int q, Carve& cv, ZRowsN& Z) {
+    for (int t = 0; t < ZRowsN::MAXT; t++) {
+        Z.exp[t] = cv.take((size_t)4 * std::max(pmax, 1) * std::max(q, 1));
+        Z.pk[t] = cv.take((size_t)k0p_of(2 * pmax) * rows_gemm_qp(2 * q) + 64);
+    }
+}
+
+int zrowsn(const ZRowsN& Z, int64_t nrows, const dcplx* X, int64_t ldx, dcplx* Out, int64_t ldo, int q,
+           std::initializer_list<ZTerm> terms, hipStream_t st) {
+    RowsGemm g{};
+    g.nrows = nrows;
+    g.X = (const double*)X;
+    g.ldx = 2 * ldx;
+    g.Out = (double*)Out;
+    g.ldo = 2 * ldo;
+    g.q = 2 * q;
+    g.nterm = 0;
+    const int qp = rows_gemm_qp(2 * q);
+    for (const ZTerm& t : terms) {
+        const int i = g.nterm;
+        const int kpad = k0p_of(2 * t.p);
+        PROF("zexpand", st, launch_zexpand(t.p, q, t.B, t.ldb, t.sign, Z.exp[i], st));
+        PROF("pack_b", st, launch_pack_b(2 * t.p, 2 * q, Z.exp[i], 2 * q, 0, 1.0, kpad, qp, Z.pk[i], st));
+        g.t[g.nterm++] = {(const double*)t.Y, 2 * t.ldy, 2 * t.p, kpad, Z.pk[i]};
+    }
+    PROF("rows_gemm", st, launch_rows_gemm(g, st));
+    return 0;
+}
+
+struct ZBwdPlan {
+    ZXty xA, xQ, xG, xA1, xM;
+    ZRowsN rr;
+    dcplx *Pm, *Tm, *CA, *CQ, *CG, *CA1, *Z, *N, *Gb, *Yb, *A1t;
+    dcplx *Qu, *Qub;
+    dcplx *MQ, *gRu, *Mk, *CL, *RH, *RiH, *CM;
+    dcplx *Tb, *Pb, *TmI, *TbL, *M1, *CL1, *B1m, *Li;
+    size_t bytes;
+};
+
+void make_zbwd_plan(int64_t n, int64_t k0, int64_t k, void* ws, ZBwdPlan& P) {
+    Carve cv(ws);
+    const int ik = (int)k, ik0 = (int)k0;
+    const size_t kk = (size_t)k * k, k0k = (size_t)std::max<int64_t>(k0, 1) * k,
+                 k00 = (size_t)std::max<int64_t>(k0, 1) * std::max<int64_t>(k0, 1);
+    zxty_plan(n - k0, ik, ik, cv, P.xM);
+    zrowsn_plan(std::max(ik0, ik), std::max(ik0, ik), cv, P.rr);
+    for (dcplx** p : {&P.MQ, &P.gRu, &P.Mk, &P.CL, &P.RH, &P.RiH, &P.CM}) *p = ztake(cv, kk);
+    P.Pm = P.Tm = P.CA = P.CQ = P.CG = P.CA1 = P.Z = P.N = P.Gb = P.Yb = P.A1t = P.Qu = P.Qub = nullptr;
+    P.Tb = P.Pb = P.TmI = P.TbL = P.M1 = P.CL1 = P.B1m = P.Li = nullptr;
+    if (k0 > 0) {
+        zxty_plan(n, ik0, ik, cv, P.xA);
+        zxty_plan(n, ik0, ik, cv, P.xQ);
+        zxty_plan(n, ik0, ik, cv, P.xG);
+        zxty_plan(n, ik0, ik, cv, P.xA1);
+        for (dcplx** p : {&P.CA, &P.CQ, &P.CG, &P.CA1, &P.Z, &P.N, &P.Gb, &P.Yb, &P.A1t}) *p = ztake(cv, k0k);
+        for (dcplx** p : {&P.Pm, &P.Tm, &P.Tb, &P.Pb, &P.TmI, &P.TbL, &P.M1, &P.CL1, &P.B1m, &P.Li})
+            *p = ztake(cv, k00);
+        P.Qu = ztake(cv, (size_t)(n - k0) * k);
+        P.Qub = ztake(cv, (size_t)(n - k0) * k);
+    }
+    P.bytes = cv.bytes();
+}
+
+}  // namespace
+
+namespace tho {
+
+size_t ztwo_stage_backward_bytes(int64_t n, int64_t k0, int64_t k) {
+    if (k == 0) return 0;
+    ZBwdPlan P;
+    make_zbwd_plan(n, k0, k, nullptr, P);
+    return P.bytes;
+}
+
+int run_ztwo_stage_backward(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A,
+                            int64_t lda, const dcplx* Q, int64_t ldq, const dcplx* R, int64_t ldr, const dcplx* gQ,
+                            int64_t ldgq, const dcplx* gR, int64_t ldgr, const dcplx* gS, int64_t ldgs, dcplx* dV,
+                            int64_t lddv, dcplx* dA, int64_t ldda, void* ws, hipStream_t st) {
+    int rc = 0;
+    ZBwdPlan P;
+    make_zbwd_plan(n, k0, k, ws, P);
+    const int ik = (int)k, ik0 = (int)k0;
+    const int64_t m = n - k0;
+    const dcplx *Qu = Q + k0 * ldq, *Qub = gQ + k0 * ldgq;
+    int64_t ldqu = ldq, ldqub = ldgq;
+    if (k0 > 0) {
+        // P, T again (side stream) beside the reductions V^H A, V^H Q, V^H G_Q
+        Fork& f = fork_for_thread();
+        if (!f.ok) return set_err(THO_E_HIP, "could not create the side stream");
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        PROF("zqr_top", f.side, launch_zqr_top(ik0, V, ldv, P.Pm, P.Tm, f.side));
+        HIPCHK(hipEventRecord(f.ev1, f.side));
+        if ((rc = zxty(P.xA, n, V, ldv, ik0, A, lda, ik, 1.0, P.CA, k, st))) return rc;
+        if ((rc = zxty(P.xQ, n, V, ldv, ik0, Q, ldq, ik, 1.0, P.CQ, k, st))) return rc;
+        if ((rc = zxty(P.xG, n, V, ldv, ik0, gQ, ldgq, ik, 1.0, P.CG, k, st))) return rc;
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
+        // Z = T^{-H} (P^H A_top - V^H A)
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 2, A, lda, 0, -1, 0, P.CA, k, P.Z, k, st));
+        PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 2, P.Z, k, st));
+        // N = -T^{-H} W^H Q  (W^H W = T + T^H for orthonormal V)
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 2, Q, ldq, 0, 1, 0, P.CQ, k, P.N, k, st));
+        PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 2, P.N, k, st));
+        // G_bar = T^{-H} N_bar, N_bar = -W^H Q_bar
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 2, gQ, ldgq, 0, 1, 0, P.CG, k, P.Gb, k, st));
+        PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 2, P.Gb, k, st));
+        // Q_ = Q_low - V_low N ;  Q__bar = Q_bar_low - V_low G_bar
+        if ((rc = zrowsn(P.rr, m, Q + k0 * ldq, ldq, P.Qu, k, ik, {{V + k0 * ldv, ldv, ik0, P.N, k, -1.0}}, st)))
+            return rc;
+        if ((rc = zrowsn(P.rr, m, gQ + k0 * ldgq, ldgq, P.Qub, k, ik, {{V + k0 * ldv, ldv, ik0, P.Gb, k, -1.0}}, st)))
+            return rc;
+        Qu = P.Qu;
+        Qub = P.Qub;
+        ldqu = ldqub = k;
+    }
+    // (QR) adjoint: A1_bar_low = (Q__bar + Q_ copyltu(M)) R^{-H},
+    // M = R triu(R_bar)^H - Q__bar^H Q_
+    if ((rc = zxty(P.xM, m, Qub, ldqub, ik, Qu, ldqu, ik, 1.0, P.MQ, k, st))) return rc;
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik, 1.0, gR, ldgr, 0, 0.0, nullptr, 0, 0, 0.0, 2, P.gRu, k, st));
+    PROF("zgemm", st, launch_zgemm(ik, ik, ik, 1, 0, R, ldr, 0, P.gRu, k, 2, -1, 0, P.MQ, k, P.Mk, k, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik, 1.0, P.Mk, k, 0, 0.0, nullptr, 0, 0, 0.0, 3, P.CL, k, st));
+    // R^{-H}: solve R^H X = I with R^H stored lower
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik, 1.0, R, ldr, 2, 0.0, nullptr, 0, 0, 0.0, 1, P.RH, k, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik, 0.0, nullptr, 0, 0, 0.0, nullptr, 0, 0, 1.0, 0, P.RiH, k, st));
+    PROF("ztrsm", st, launch_ztrsm(ik, ik, P.RH, k, 0, P.RiH, k, st));
+    PROF("zgemm", st, launch_zgemm(ik, ik, ik, 1, 0, P.CL, k, 0, P.RiH, k, 0, 0, 0, nullptr, 0, P.CM, k, st));
+    if ((rc = zrowsn(P.rr, m, nullptr, 0, dA + k0 * ldda, ldda, ik,
+                     {{Qub, ldqub, ik, P.RiH, k, 1.0}, {Qu, ldqu, ik, P.CM, k, 1.0}}, st)))
+        return rc;
+    if (k0 == 0) return 0;
+
+    // (S) adjoint: A1_bar_top = P S_bar
+    if (gS)
+        PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 0, gS, ldgs, 0, 0, 0, nullptr, 0, dA, ldda, st));
+    else
+        PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik, 0.0, nullptr, 0, 0, 0.0, nullptr, 0, 0, 0.0, 0, dA, ldda, st));
+    // (A) adjoint: Y_bar = T^{-1} Z_bar, Z_bar = -W^H A1_bar = V^H A1_bar - P^H A1_bar_top
+    if ((rc = zxty(P.xA1, n, V, ldv, ik0, dA, ldda, ik, 1.0, P.CA1, k, st))) return rc;
+    PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 2, dA, ldda, 0, 1, 0, P.CA1, k, P.Yb, k, st));
+    PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 0, P.Yb, k, st));
+    // T_bar = -G_bar N^H - Z Y_bar^H
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik, -1, 0, P.Gb, k, 0, P.N, k, 2, 0, 0, nullptr, 0, P.Tb, k0, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik, -1, 0, P.Z, k, 0, P.Yb, k, 2, 1, 0, P.Tb, k0, P.Tb, k0, st));
+    // V_bar = -W_bar = Q_bar N^H - [0; Q_] G_bar^H + A1_bar Z^H - A Y_bar^H
+    // (B operands are the conjugate transposes, k x k0)
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik0, 1.0, P.N, k, 2, 0.0, nullptr, 0, 0, 0.0, 0, P.CA, k0, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik0, 1.0, P.Z, k, 2, 0.0, nullptr, 0, 0, 0.0, 0, P.CQ, k0, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik0, 1.0, P.Yb, k, 2, 0.0, nullptr, 0, 0, 0.0, 0, P.CG, k0, st));
+    if ((rc = zrowsn(P.rr, n, nullptr, 0, dV, lddv, ik0,
+                     {{gQ, ldgq, ik, P.CA, k0, 1.0}, {dA, ldda, ik, P.CQ, k0, 1.0}, {A, lda, ik, P.CG, k0, -1.0}},
+                     st)))
+        return rc;
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik, ik0, 1.0, P.Gb, k, 2, 0.0, nullptr, 0, 0, 0.0, 0, P.CA, k0, st));
+    if ((rc = zrowsn(P.rr, m, dV + k0 * lddv, lddv, dV + k0 * lddv, lddv, ik0, {{P.Qu, k, ik, P.CA, k0, -1.0}}, st)))
+        return rc;
+    // P_bar = A1_top S_bar^H + W_bar_top,  A1_top = A_top - (P - V_top) Z
+    PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.Z, k, 0, 1, 0, A, lda, P.A1t, k, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, V, ldv, 0, P.Z, k, 0, 1, 0, P.A1t, k, P.A1t, k, st));
+    if (gS)
+        PROF("zgemm", st, launch_zgemm(ik0, ik0, ik, 1, 0, P.A1t, k, 0, gS, ldgs, 2, -1, 0, dV, lddv, P.Pb, k0, st));
+    else
+        PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik0, -1.0, dV, lddv, 0, 0.0, nullptr, 0, 0, 0.0, 0, P.Pb, k0, st));
+    // A_bar = A1_bar + W Y_bar: bottom rows - V_low Y_bar, top rows + (P - V_top) Y_bar
+    if ((rc = zrowsn(P.rr, m, dA + k0 * ldda, ldda, dA + k0 * ldda, ldda, ik, {{V + k0 * ldv, ldv, ik0, P.Yb, k, -1.0}},
+                     st)))
+        return rc;
+    PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 0, P.Yb, k, 0, 1, 0, dA, ldda, dA, ldda, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, V, ldv, 0, P.Yb, k, 0, 1, 0, dA, ldda, dA, ldda, st));
+    // (P, T) adjoint: V_top = Q1 R1, Q1 = -P, R1 = (T - I)^H, Q1_bar = -P_bar,
+    // R1_bar = tril(T_bar)^H:  M1 = (T - I)^H tril(T_bar) - P_bar^H P,
+    // V_bar_top += (-P_bar - P copyltu(M1)) (T - I)^{-1}
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik0, 1.0, P.Tm, k0, 0, 0.0, nullptr, 0, 0, -1.0, 1, P.TmI, k0, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik0, 1.0, P.Tb, k0, 0, 0.0, nullptr, 0, 0, 0.0, 1, P.TbL, k0, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik0, 1, 0, P.TmI, k0, 2, P.TbL, k0, 0, 0, 0, nullptr, 0, P.M1, k0, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik0, -1, 0, P.Pb, k0, 2, P.Pm, k0, 0, 1, 0, P.M1, k0, P.M1, k0, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik0, 1.0, P.M1, k0, 0, 0.0, nullptr, 0, 0, 0.0, 3, P.CL1, k0, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik0, -1, 0, P.Pm, k0, 0, P.CL1, k0, 0, -1, 0, P.Pb, k0, P.B1m, k0, st));
+    PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik0, 0.0, nullptr, 0, 0, 0.0, nullptr, 0, 0, 1.0, 0, P.Li, k0, st));
+    PROF("ztrsm", st, launch_ztrsm(ik0, ik0, P.TmI, k0, 0, P.Li, k0, st));
+    PROF("zgemm", st, launch_zgemm(ik0, ik0, ik0, 1, 0, P.B1m, k0, 0, P.Li, k0, 0, 1, 0, dV, lddv, dV, lddv, st));
+    return 0;
+}
+
+}  // namespace tho

@@ -160,6 +160,11 @@ int run_zbcgs(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, con
               int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, int proj, int rounds, void* ws,
               hipStream_t st);
 size_t zhhqr_bytes(int64_t n, int64_t k0, int64_t k);
+size_t ztwo_stage_backward_bytes(int64_t n, int64_t k0, int64_t k);
+int run_ztwo_stage_backward(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A,
+                            int64_t lda, const dcplx* Q, int64_t ldq, const dcplx* R, int64_t ldr, const dcplx* gQ,
+                            int64_t ldgq, const dcplx* gR, int64_t ldgr, const dcplx* gS, int64_t ldgs, dcplx* dV,
+                            int64_t lddv, dcplx* dA, int64_t ldda, void* ws, hipStream_t st);
 int run_zhhqr(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv, const dcplx* A, int64_t lda, dcplx* Q,
               int64_t ldq, dcplx* R, int64_t ldr, dcplx* S, int64_t lds, void* ws, hipStream_t st);
 

@@ -132,6 +132,9 @@ hipError_t launch_zexpand(int p, int q, const void* B, int64_t ldb, double sign,
 hipError_t launch_zfinish_r(int k, int KP, const void* Rin, int64_t ldri, void* Rout, int64_t ldr, void* G0,
                             hipStream_t st);
 hipError_t launch_zcopy(int64_t M, int N, const void* src, int64_t lds, void* dst, int64_t ldd, hipStream_t st);
+// D = a op(X) + b op(Y) + c I, complex, masked (mode 1 lower, 2 upper, 3 copyltu).
+hipError_t launch_zsmall_ew(int M, int N, double a, const void* X, int64_t ldx, int opx, double b, const void* Y,
+                            int64_t ldy, int opy, double c, int mode, void* D, int64_t ldd, hipStream_t st);
 
 // One problem of the batched path (k_batched.hip): inputs/outputs as in
 // tho_two_stage plus its own workspace pieces (all device pointers).
