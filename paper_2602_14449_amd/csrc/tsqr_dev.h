@@ -177,7 +177,14 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
             const double nrm = sqrt(alpha * alpha + sig2);
             beta = (alpha < 0.0) ? nrm : -nrm;
             const double amb = alpha - beta;
-            const double r = 1.0 / (beta * amb);
+            // 1 / (beta amb) by the hardware reciprocal and two Newton steps
+            // (within an ulp or two; |beta amb| >= sig2 is a normal number
+            // over the documented input range) -- a shorter dependency chain
+            // than the correctly rounded division
+            const double dd = beta * amb;
+            double r = __builtin_amdgcn_rcp(dd);
+            r = fma(r, fma(-dd, r, 1.0), r);
+            r = fma(r, fma(-dd, r, 1.0), r);
             tau = -(amb * amb) * r;
             scale = beta * r;
         }
