@@ -297,8 +297,11 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k,
  * first from a device work counter.  Plan creation validates the problems,
  * lays out each problem's part of the caller's workspace, autotunes the tile
  * height (128 or 256 rows) and the number of persistent workgroups by timing
- * them on the batch itself (cached per batch signature for the life of the
- * process), and captures the launches into a HIP graph.  The plan binds the
+ * them on the batch itself (cached per batch signature and device for the
+ * life of the process and, when the environment variable THO_TUNE_CACHE
+ * names a file, in that file across processes: one text line per choice,
+ * read at the first plan creation and appended after each new tuning), and
+ * captures the launches into a HIP graph.  The plan binds the
  * problem pointers and the workspace: tho_batched_run replays the graph on
  * `stream` and may be called any number of times while the buffers live.
  * Plan creation allocates small device descriptor arrays (freed by

@@ -4,10 +4,14 @@
 // Plan creation validates the problems, lays out each problem's workspace,
 // orders the problems longest first, picks the tile height (128 or 256 rows)
 // and the number of persistent workgroups by timing the candidates on the
-// actual batch (the choice is cached per batch signature for the process),
+// actual batch (the choice is cached per batch signature and device for the
+// process, and in the file THO_TUNE_CACHE names, if set),
 // and captures the launch sequence (counter reset + one persistent kernel per
 // column-width class) into a graph that tho_batched_run replays.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <tuple>
 
@@ -38,8 +42,53 @@ namespace {
 
 constexpr int MIN_TILE = 128;  // smallest candidate tile height
 
+// Autotuner results: process-global, and shared across processes through a
+// text file when the environment variable THO_TUNE_CACHE names one.  A line
+// of the file is
+//     tho-batched-v1 <arch> <compute units> <count> <sum n> <sum k0> <sum k> <tile blocks> <grid>
+// (the batch signature, the device it was measured on, the choice); lines
+// that do not parse or belong to another device are ignored.
+using TuneKey = std::tuple<std::string, int, int, int64_t, int64_t, int64_t>;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::pair<int, int>> g_tune_cache;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+bool g_tune_file_read = false;
+
+const char* tune_file() {
+    const char* f = std::getenv("THO_TUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+// Under g_tune_mu.
+void tune_file_load() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = tune_file();
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512], arch[128];
+    while (std::fgets(line, sizeof line, f)) {
+        int cus = 0, count = 0, rbo = 0, grid = 0;
+        long long sn = 0, sk0 = 0, sk = 0;
+        if (std::sscanf(line, "tho-batched-v1 %127s %d %d %lld %lld %lld %d %d", arch, &cus, &count, &sn, &sk0, &sk,
+                        &rbo, &grid) == 8 &&
+            (rbo == 2 || rbo == 4) && grid > 0)
+            g_tune_cache[TuneKey(arch, cus, count, sn, sk0, sk)] = {rbo, grid};
+    }
+    std::fclose(f);
+}
+
+// Under g_tune_mu; best effort (a cache that cannot be written is not an error).
+void tune_file_append(const TuneKey& k, int rbo, int grid) {
+    const char* path = tune_file();
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "tho-batched-v1 %s %d %d %lld %lld %lld %d %d\n", std::get<0>(k).c_str(), std::get<1>(k),
+                 std::get<2>(k), (long long)std::get<3>(k), (long long)std::get<4>(k), (long long)std::get<5>(k), rbo,
+                 grid);
+    std::fclose(f);
+}
 
 size_t inst_doubles(int64_t n, int64_t k0, int64_t k) {
     const int KP = kp_of(k), K0P = k0p_of(k0);
@@ -270,10 +319,16 @@ int tho_batched_plan_create(int32_t count, const tho_problem_t* probs, void* ws,
     int dev = 0, cus = 256;
     PCHK(hipGetDevice(&dev));
     PCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const auto key = std::make_tuple(P->count, sig_n, sig_k0, sig_k);
+    hipDeviceProp_t prop;
+    PCHK(hipGetDeviceProperties(&prop, dev));
+    std::string arch(prop.gcnArchName);
+    for (char& ch : arch)
+        if (ch == ' ' || ch == '\n') ch = '_';
+    const TuneKey key(arch, cus, P->count, sig_n, sig_k0, sig_k);
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_file_load();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             P->rbo = it->second.first;
@@ -312,6 +367,7 @@ int tho_batched_plan_create(int32_t count, const tho_problem_t* probs, void* ws,
         P->tuned_ms = best;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = {P->rbo, P->grid};
+        tune_file_append(key, P->rbo, P->grid);
     }
     // capture the launch sequence once
     PCHK(hipStreamBeginCapture(P->cs, hipStreamCaptureModeThreadLocal));

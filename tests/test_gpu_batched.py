@@ -92,3 +92,40 @@ def test_batched_full_workload_sampled():
         Q1, R1, S1 = tho.two_stage(V, A)
         assert np.abs(to_host(Q1) - to_host(Q)).max() < 1e-10
     plan.close()
+
+
+_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+import paper_2602_14449_amd as tho
+import tho_workloads as W
+g = np.random.default_rng(4242)
+pairs = []
+for n, k0, k in [(3001, 8, 4), (5003, 16, 8), (7007, 32, 16)]:
+    pairs.append((torch.from_numpy(W.orthonormal(g, n, k0)).cuda(), torch.from_numpy(g.standard_normal((n, k))).cuda()))
+plan = tho.BatchedPlan(pairs)
+info = plan.info()
+print("TUNE", info["tile_rows"], info["workgroups"], info["tuned_ms"])
+"""
+
+
+def test_tuner_cache_file(tmp_path):
+    # THO_TUNE_CACHE: the first process tunes and appends its choice to the
+    # file; a second process with the same batch reads it back without tuning
+    require_gpu()
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, THO_TUNE_CACHE=str(tmp_path / "tune.txt"))
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", _CHILD % root], env=env, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        line = [x for x in r.stdout.splitlines() if x.startswith("TUNE")][-1].split()
+        outs.append((int(line[1]), int(line[2]), float(line[3])))
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("tho-batched-v1 ")
+    assert outs[0][2] > 0.0 and outs[1][2] == 0.0           # tuned, then read from the file
+    assert outs[0][:2] == outs[1][:2]
