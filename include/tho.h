@@ -236,6 +236,29 @@ int tho_block_householder_step(int32_t dtype, int64_t n, int32_t i, const int64_
                                int64_t lda, void* Q, int64_t ldq, void* R, int64_t ldr, const tho_opts_t* opts,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* Two-stage orthogonalization in the weighted inner product
+ * <x, y>_B = x^* diag(b) y (Algorithm 3, §5, with a diagonal positive
+ * definite B = diag(b)): given V with V^* B V = I and A, returns Q, R, S with
+ * [V, A] = [V, Q] [[I, S], [0, R]] and [V, Q]^* B [V, Q] = I.  With
+ * D = diag(sqrt(b)), the generalized Householder transformation of
+ * Theorem 4 is D^{-1} H~ D (H~ the Euclidean one for the scaled data) and the
+ * initial B-orthonormal basis of §5 is D^{-1} [I; 0], so the method is
+ * Algorithm 1 on (D V, D A) followed by Q = D^{-1} Q~: the rows are scaled in
+ * streaming kernels around tho_two_stage (opts as there, including
+ * p_choice and the THO_CHECK_* flags, which then apply to D V and D A).
+ * Arguments: 1 dtype, 2 n, 3 k0, 4 k, 5 b (n doubles, device, all > 0; a
+ * nonpositive entry gives NaN, reported by THO_CHECK_FINITE), 6-15 V .. lds as
+ * arguments 5-14 of tho_two_stage, 16 opts, 17 ws, 18 ws_bytes, 19 stream.
+ * The workspace holds tho_two_stage's own first (tho_get_info(ws) reads the
+ * info word as for tho_two_stage) and then scaled copies of V and A.  A
+ * general (non-diagonal) B is not supported. */
+int tho_two_stage_weighted_workspace(int32_t dtype, int64_t n, int64_t k0, int64_t k, const tho_opts_t* opts,
+                                     size_t* bytes);
+int tho_two_stage_weighted(int32_t dtype, int64_t n, int64_t k0, int64_t k, const double* b,
+                           const void* V, int64_t ldv, const void* A, int64_t lda,
+                           void* Q, int64_t ldq, void* R, int64_t ldr, void* S, int64_t lds,
+                           const tho_opts_t* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* Block classical Gram-Schmidt, the baseline of eq. (1) and Table 1:
  * `rounds` rounds, each running `proj` projections
  *     C = V^T X,  X <- X - V C,  S_r <- S_r + C          (BQR-1)

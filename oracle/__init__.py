@@ -21,6 +21,11 @@ Modules
                modified LU of Algorithm 2, QR, polar decomposition)
   two_stage    the two-stage method from the definitions of §3.1 (eq. (3),
                eq. (4)), any choice of P
+  b_inner      the two-stage method in a B-inner product (Algorithm 3,
+               Theorem 4, §5) and its definition through the Cholesky
+               transform
+  block_householder  Algorithm 4 (block Householder-QR, §6.1) and the block
+               BCGS2 baseline of Table 5
   appendix_a   the matrix U of eq. (6) and the Appendix A construction of an
                orthonormal V whose modified LU returns it (Example 4)
   baselines    Householder QR of [V, A] (start of §3) and the BCGS framework

@@ -8,9 +8,9 @@ has not been built.
 """
 
 from . import _lib  # noqa: F401  (raises ImportError when libtho.so is absent)
-from .api import (two_stage, workspace_bytes, get_info, block_householder, BlockHouseholder, bcgs, hhqr_full, hhqr_full_workspace_bytes,  # noqa: F401
+from .api import (two_stage, two_stage_weighted, workspace_bytes, get_info, block_householder, BlockHouseholder, bcgs, hhqr_full, hhqr_full_workspace_bytes,  # noqa: F401
                   two_stage_backward, two_stage_autograd, TwoStageFunction,
                   BatchedPlan, two_stage_batched)
 
-__all__ = ["two_stage", "workspace_bytes", "get_info", "block_householder", "BlockHouseholder", "bcgs", "hhqr_full", "hhqr_full_workspace_bytes", "two_stage_backward",
+__all__ = ["two_stage", "two_stage_weighted", "workspace_bytes", "get_info", "block_householder", "BlockHouseholder", "bcgs", "hhqr_full", "hhqr_full_workspace_bytes", "two_stage_backward",
            "two_stage_autograd", "TwoStageFunction", "BatchedPlan", "two_stage_batched"]

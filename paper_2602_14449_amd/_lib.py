@@ -58,6 +58,13 @@ tho_block_householder_step = _proto(
     "tho_block_householder_step", ctypes.c_int,
     [c_i32, c_i64, c_i32, ctypes.POINTER(c_i64), c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
      ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
+tho_two_stage_weighted_workspace = _proto(
+    "tho_two_stage_weighted_workspace", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, ctypes.POINTER(Opts), ctypes.POINTER(c_sz)])
+tho_two_stage_weighted = _proto(
+    "tho_two_stage_weighted", ctypes.c_int,
+    [c_i32, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+     c_i64, c_vp, c_i64, ctypes.POINTER(Opts), c_vp, c_sz, c_vp])
 tho_get_info = _proto("tho_get_info", ctypes.c_int, [c_vp, ctypes.POINTER(c_i32)])
 CHECK_FINITE = 1
 CHECK_VORTH = 2
@@ -109,6 +116,7 @@ tho_plan_destroy = _proto("tho_plan_destroy", ctypes.c_int, [c_vp])
 EXPORTED = ["tho_version", "tho_last_error", "tho_strerror",
             "tho_two_stage_workspace", "tho_two_stage", "tho_two_stage_noalloc", "tho_get_info",
             "tho_block_householder_workspace", "tho_block_householder", "tho_block_householder_step",
+            "tho_two_stage_weighted_workspace", "tho_two_stage_weighted",
             "tho_hhqr_full_workspace", "tho_hhqr_full",
             "tho_bcgs_workspace", "tho_bcgs",
             "tho_two_stage_backward_workspace", "tho_two_stage_backward",

@@ -215,6 +215,30 @@ class BlockHouseholder:
         return self.Q[:, c0:c0 + ki], self.R[:c0 + ki, c0:c0 + ki]
 
 
+def two_stage_weighted(V, A, b, *, p_choice="qr", check_finite=False, check_vorth=False, out=None,
+                       workspace=None):
+    """Two-stage method in the weighted inner product <x, y> = x^* diag(b) y
+    (Algorithm 3 with a diagonal B): returns (Q, R, S) with
+    [V, A] = [V, Q] [[I, S], [0, R]] and [V, Q]^* diag(b) [V, Q] = I."""
+    code, n, k0, k = _check_inputs(V, A)
+    if not isinstance(b, torch.Tensor) or b.dtype != torch.float64 or b.shape != (n,) or b.device != A.device:
+        raise ValueError("b must be a float64 tensor of shape (n,) on the inputs' device")
+    b = b.contiguous()
+    Q, R, S = _outputs(out, n, k0, k, A)
+    o = _opts("fp64", p_choice, check_finite, check_vorth)
+    nb = L.c_sz(0)
+    L.check(L.tho_two_stage_weighted_workspace(code, n, k0, k, ctypes.byref(o), ctypes.byref(nb)),
+            "tho_two_stage_weighted_workspace")
+    workspace = _workspace(nb.value, workspace, A.device)
+    rc = L.tho_two_stage_weighted(code, n, k0, k, b.data_ptr(),
+                                  _ptr(V), _ld(V, "V"), A.data_ptr(), _ld(A, "A"),
+                                  Q.data_ptr(), _ld(Q, "Q"), R.data_ptr(), _ld(R, "R"),
+                                  _ptr(S), _ld(S, "S") if k0 > 0 else max(k, 1),
+                                  ctypes.byref(o), workspace.data_ptr(), workspace.numel(), _stream(A.device))
+    L.check(rc, "tho_two_stage_weighted")
+    return Q, R, S
+
+
 def get_info(workspace=None):
     """Info word of the last two_stage call on ``workspace`` (None: the
     static scratch of the no-allocation entry point on the current device):

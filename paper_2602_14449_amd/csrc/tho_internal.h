@@ -71,6 +71,11 @@ hipError_t launch_mlu_top(int n, const double* Vt, int64_t ldv, double* P, doubl
 hipError_t launch_polar_top(int n, const double* Vt, int64_t ldv, double* P, double* C, double* ws, hipStream_t st);
 size_t pchoice_ws_doubles(int n);
 
+// Y = diag(sqrt(b)) X (inv = 0) or diag(1 / sqrt(b)) X (inv = 1), n rows of
+// w doubles (k_weighted.hip).
+hipError_t launch_row_scale(int64_t n, int w, const double* b, int inv, const double* X, int64_t ldx, double* Y,
+                            int64_t ldy, hipStream_t st);
+
 // Numerical-condition checks (k_checks.hip): the info word is INT_MAX until
 // a condition lowers it (atomicMin) to its code.
 hipError_t launch_info_reset(int* info, hipStream_t st);
