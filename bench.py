@@ -153,7 +153,9 @@ def time_steps(fn, steps, warmup, stream):
     return ms, _lib.profile_read()
 
 
-def roofline(prof, model_fn, bound):
+def roofline(prof, model_fn, bound, traffic_tag=None):
+    """`traffic_tag` names the workload the committed HBM counters were taken
+    on; the traffic field stays null for any other workload."""
     dname, (dms, dcnt) = max(prof.items(), key=lambda kv: kv[1][0])
     davg = dms / max(dcnt, 1)
     model = model_fn(dname)
@@ -170,9 +172,10 @@ def roofline(prof, model_fn, bound):
             "frac": round(ach / peak, 4), "traffic": None, "kernel": dname, "avg_ms": round(davg, 4),
             "alg_bytes_per_launch": bts, "alg_flops_per_launch": fl}
     tf = os.path.join(HERE, "profiles", "traffic.json")
-    if os.path.exists(tf):
+    if traffic_tag is not None and os.path.exists(tf):
         try:
-            ent = json.load(open(tf)).get(dname)
+            tj = json.load(open(tf))
+            ent = tj.get(dname) if tj.get("_calibration", {}).get("workload") == traffic_tag else None
             if ent and ent.get("valid", False):
                 roof["traffic"] = ent["bytes_per_launch"]
         except Exception:
@@ -232,10 +235,11 @@ def run_graded(a, panel):
     wl = ("graded: real two-stage, n=2^22, k0=128, k=64, cond(A)=1e8, %s panels" % panel.upper()) if full \
         else "graded: n=%d, k0=%d, k=%d, %s panels" % (n, k0, k, panel)
     out = base_line(a, "two-stage orth GB/s (% HBM peak) vs full HHQR of [V,A]; orth loss vs FP64", gbs, ms,
-                    "f64", wl, {"n": n, "k0": k0, "k": k, "panel": panel})
+                    "f64" if panel == "fp64" else panel + "+f64", wl, {"n": n, "k0": k0, "k": k, "panel": panel})
     out["pct_hbm_peak"] = round(100.0 * gbs / HBM_PEAK_GBS, 2)
     out["pct_fp64_peak"] = round(100.0 * F_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 2)
-    out["roofline"] = roofline(prof, lambda nm: kernel_model(nm, n, k0, k), "mfma")
+    out["roofline"] = roofline(prof, lambda nm: kernel_model(nm, n, k0, k), "mfma",
+                               traffic_tag="graded n=%d k0=%d k=%d panel=%s" % (n, k0, k, panel))
     out["kernels_ms_per_step"] = {kn: round(v[0] / a.steps, 4) for kn, v in
                                   sorted(prof.items(), key=lambda kv: -kv[1][0])}
     if not a.no_check:

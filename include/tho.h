@@ -70,8 +70,9 @@ typedef enum { THO_P_QR = 0, THO_P_MLU = 1, THO_P_POLAR = 2 } tho_pchoice_t;
  * the T factors always stay FP64.  THO_PANEL_F32X2 splits each FP64 operand
  * into an FP32 hi + lo pair (three FP32 MFMA products, FP32 accumulation
  * inside each MFMA block, FP64 across blocks); THO_PANEL_BF16 rounds the
- * operands to BF16 (FP32 accumulation).  Reduced-precision panels trade the
- * orthogonality of Q (about 1e-7 and 1e-3 respectively) for speed. */
+ * operands to BF16 (FP32 accumulation).  Reduced-precision panels lose
+ * orthogonality of Q (to about 1e-8 and 1e-3 respectively) and on MI355X are
+ * not faster than FP64 panels, whose Householder core dominates the time. */
 typedef enum { THO_PANEL_F64 = 0, THO_PANEL_F32X2 = 1, THO_PANEL_BF16 = 2 } tho_panel_t;
 
 /* Optional numerical-condition checks of tho_two_stage (opts->flags, OR of):
