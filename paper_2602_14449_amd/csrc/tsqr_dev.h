@@ -81,42 +81,35 @@ struct FormLds {
     static constexpr int total = KP * LDT + KP * LDT;
 };
 
-// Householder QR of the register tile x (PLAIN: the tile alone; otherwise
-// [slot; tile] with the running triangle in `slot`).  One cross-wavefront
-// exchange per column: every wavefront reduces, over its "sub" rows (below
-// the pivot), the dot products d_c of the unscaled pivot column with every
-// column c.  With the pivot-row values p_c and the reflector
-// u = [1; x_sub / (alpha - beta)]:
-//   sigma^2 = d_j,   w_c = u^T x_c = p_c + d_c / (alpha - beta),
-// and for c < j, w_c = u_c^T u_j feeds the T recurrence (Gm).
-// Returns beta of the last column; for a structured tile the caller stores it
-// into slot(k-1, k-1) after the next workgroup barrier (other wavefronts read
-// that entry as the pivot of the last column until then).
-template <int KP, bool PLAIN, int RBO, int NWT = NW>
-__device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][KP / 16], int k, int w, double* xcol,
-                                                 double* prow, double* part, double* slot, double* Gm,
-                                                 double* taus) {
+// State handed from one Householder column to the next.
+struct HhCarry {
+    double beta_prev;  // beta of the previous reflector
+    double rnew;       // structured: my entry of the previous pivot row after its reflector
+    double myscale;    // 1 / (alpha - beta) of the reflector of column `lane` (0 until then)
+};
+
+// Columns 16 CTJ .. min(16 CTJ + 16, k) - 1 of the Householder QR of the
+// register tile (see householder_tile).  With the pivot column block a
+// compile-time constant, the block selections are static: only the pivot
+// block's lanes take a lane mask, blocks left of it (Householder vectors) are
+// not updated, and no scalar branches are spent on the block index.
+template <int KP, bool PLAIN, int RBO, int NWT, int CTJ>
+__device__ __forceinline__ void householder_block(d4 (&x)[(Geo<KP, RBO>::RB)][KP / 16], int k, int w,
+                                                  double* xcol, double* prow, double* part, double* slot,
+                                                  double* Gm, double* taus, HhCarry& cy) {
     constexpr int RB = Geo<KP, RBO>::RB, RPW = Geo<KP, RBO>::RPW;
     constexpr int CT = KP / 16;
     constexpr int LDT = KP + 1;
     const int l = opaque_lane(), g = l >> 4, cl = l & 15;
-    double tau_prev = 0.0, beta_prev = 0.0, wl_prev = 0.0;
     double* xw = xcol + RPW * w;  // this wavefront's pivot column, lane-group order
-    for (int j = 0; j < k; j++) {
-        const int pb = j & 1, ctj = j >> 4, clj = j & 15;
-        // (ct == ctj is uniform: the empty asm keeps it a scalar branch, so
-        // the three other column blocks cost nothing)
+    const int jend = (16 * CTJ + 16 < k) ? 16 * CTJ + 16 : k;
+    for (int j = 16 * CTJ; j < jend; j++) {
+        const int pb = j & 1, clj = j & 15;
+        if (cl == clj) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            if (ct == ctj) {
-                asm volatile("");
-                if (cl == clj) {
+            for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                    for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) xw[rb * 16 + g * 4 + v] = x[rb][ct][v];
-                }
-            }
+                for (int v = 0; v < 4; v++) xw[rb * 16 + g * 4 + v] = x[rb][CTJ][v];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -131,7 +124,8 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
             }
         {
             // CT independent dot products, interleaved so that the FMA chains
-            // and the cross-lane reductions pipeline
+            // and the cross-lane reductions pipeline (blocks left of the
+            // pivot give the Gram of the Householder vectors for T)
             double sc[CT];
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) sc[ct] = 0.0;
@@ -157,52 +151,60 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
         }
         __syncthreads();
 
-        // deferred update of slot row j-1 (all its readers are past the barrier)
+        // row j-1 of the slot after its reflector (every reader of the old
+        // row is past the barrier); plain stores, computed last column
         if (!PLAIN && j > 0 && w == 0) {
-            if (l > j - 1 && l < k) slot[(j - 1) * LDT + l] -= tau_prev * wl_prev;
-            if (l == j - 1) slot[(j - 1) * LDT + (j - 1)] = beta_prev;
+            if (l > j - 1 && l < k) slot[(j - 1) * LDT + l] = cy.rnew;
+            if (l == j - 1) slot[(j - 1) * LDT + (j - 1)] = cy.beta_prev;
         }
         double dl = 0.0, pl = 0.0;
         if (l < KP) {
+            double pp[NWT];
 #pragma unroll
-            for (int ww = 0; ww < NWT; ww++) dl += part[(pb * NWT + ww) * KP + l];
+            for (int ww = 0; ww < NWT; ww++) pp[ww] = part[(pb * NWT + ww) * KP + l];
             pl = PLAIN ? prow[pb * KP + l] : slot[j * LDT + l];
+#pragma unroll
+            for (int ww = 0; ww < NWT; ww++) dl += pp[ww];
         }
         const double sig2 = bcast(dl, j);
         const double alpha = bcast(pl, j);
         double beta = alpha, tau = 0.0, scale = 0.0;
         if (sig2 != 0.0) {
-            // one division: r = 1 / (beta (alpha - beta)) gives
-            // 1 / (alpha - beta) = beta r and tau = (beta - alpha) / beta = -(alpha - beta)^2 r
-            const double nrm = sqrt(alpha * alpha + sig2);
+            // beta = -sign(alpha) sqrt(alpha^2 + sigma^2) from the hardware
+            // reciprocal square root r (two Newton steps), then one Newton
+            // step for the root; tau = (beta - alpha) / beta = 1 + |alpha| r
+            // needs no division, and the reflector's scale 1 / (alpha - beta)
+            // is the hardware reciprocal with two Newton steps.  s is a
+            // normal number over the documented input range.
+            const double s2 = fma(alpha, alpha, sig2);
+            double r = __builtin_amdgcn_rsq(s2);
+            r = fma(0.5 * r, fma(-s2 * r, r, 1.0), r);
+            r = fma(0.5 * r, fma(-s2 * r, r, 1.0), r);
+            double nrm = s2 * r;
+            nrm = fma(0.5 * r, fma(-nrm, nrm, s2), nrm);
             beta = (alpha < 0.0) ? nrm : -nrm;
+            tau = fma(fabs(alpha), r, 1.0);
             const double amb = alpha - beta;
-            // 1 / (beta amb) by the hardware reciprocal and two Newton steps
-            // (within an ulp or two; |beta amb| >= sig2 is a normal number
-            // over the documented input range) -- a shorter dependency chain
-            // than the correctly rounded division
-            const double dd = beta * amb;
-            double r = __builtin_amdgcn_rcp(dd);
-            r = fma(r, fma(-dd, r, 1.0), r);
-            r = fma(r, fma(-dd, r, 1.0), r);
-            tau = -(amb * amb) * r;
-            scale = beta * r;
+            double q = __builtin_amdgcn_rcp(amb);
+            q = fma(q, fma(-amb, q, 1.0), q);
+            q = fma(q, fma(-amb, q, 1.0), q);
+            scale = q;
         }
+        // w_c = u^T x_c for the trailing columns; for c < j, times the scale
+        // of column c (still unscaled in the registers), u_c^T u_j for T
         const double wl = pl + scale * dl;
+        if (!PLAIN) cy.rnew = pl - tau * wl;
         if (w == 0) {
-            if (l < j) Gm[j * LDT + l] = wl;
+            if (l < j) Gm[j * LDT + l] = wl * cy.myscale;
             if (l == 0) taus[j] = tau;
         }
-        double wv4[4];
-        gather_cols(wl, wv4);
-        double wv[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) wv[ct] = wv4[ct];
-        // rank-1 update of the columns right of j.  Blocks left of the pivot
-        // block hold Householder vectors only and are skipped (uniform
-        // branch); padding columns (>= k) stay zero by themselves, as their
-        // pivot-row entries and dot products are zero.
-        double u[RB][4];  // reflector on my rows; structured: scale * xs
+        if (l == j) cy.myscale = scale;
+        double wv[4];
+        gather_cols(wl, wv);
+        // rank-1 update of the columns right of j; padding columns (>= k)
+        // stay zero by themselves, as their pivot-row entries and dot
+        // products are zero
+        double u[RB][4];  // plain: the reflector on my rows
         if (PLAIN) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
@@ -212,41 +214,69 @@ __device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][K
         }
         const double ts = PLAIN ? tau : tau * scale;
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            if (ct < ctj) continue;
-            asm volatile("");
+        for (int ct = CTJ; ct < CT; ct++) {
             const double cw = ts * wv[ct];
-            const double coef = (ct > ctj || cl > clj) ? cw : 0.0;
+            const double coef = (ct > CTJ || cl > clj) ? cw : 0.0;
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) x[rb][ct][v] -= coef * (PLAIN ? u[rb][v] : xs[rb][v]);
         }
-        // column j becomes the Householder vector (and beta on the pivot)
+        // plain: beta on the pivot (the sub-column keeps its unscaled values)
+        if (PLAIN && cl == clj) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-            if (ct != ctj) continue;
-            asm volatile("");
-            if (cl == clj) {
+            for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        if (PLAIN) {
-                            const int row = tile_row<RPW>(w, rb, l, v);
-                            if (row > j) x[rb][ct][v] = u[rb][v];
-                            else if (row == j) x[rb][ct][v] = beta;
-                        } else {
-                            x[rb][ct][v] *= scale;
-                        }
-                    }
-            }
+                for (int v = 0; v < 4; v++)
+                    if (tile_row<RPW>(w, rb, l, v) == j) x[rb][CTJ][v] = beta;
         }
-        tau_prev = tau;
-        beta_prev = beta;
-        wl_prev = wl;
+        cy.beta_prev = beta;
     }
-    return beta_prev;
+}
+
+// Householder QR of the register tile x (PLAIN: the tile alone; otherwise
+// [slot; tile] with the running triangle in `slot`).  One cross-wavefront
+// exchange per column: every wavefront reduces, over its "sub" rows (below
+// the pivot), the dot products d_c of the unscaled pivot column with every
+// column c.  With the pivot-row values p_c and the reflector
+// u = [1; x_sub / (alpha - beta)]:
+//   sigma^2 = d_j,   w_c = u^T x_c = p_c + d_c / (alpha - beta),
+// and for c < j, w_c (times the scale of column c) = u_c^T u_j feeds the T
+// recurrence (Gm).  The Householder vectors stay unscaled in the registers
+// during the loop and are scaled once at the end.  Returns beta of the last
+// column; for a structured tile the caller stores it into slot(k-1, k-1)
+// after the next workgroup barrier (other wavefronts read that entry as the
+// pivot of the last column until then).
+template <int KP, bool PLAIN, int RBO, int NWT = NW>
+__device__ __forceinline__ double householder_tile(d4 (&x)[(Geo<KP, RBO>::RB)][KP / 16], int k, int w, double* xcol,
+                                                 double* prow, double* part, double* slot, double* Gm,
+                                                 double* taus) {
+    constexpr int RB = Geo<KP, RBO>::RB, RPW = Geo<KP, RBO>::RPW;
+    constexpr int CT = KP / 16;
+    HhCarry cy = {0.0, 0.0, 0.0};
+    householder_block<KP, PLAIN, RBO, NWT, 0>(x, k, w, xcol, prow, part, slot, Gm, taus, cy);
+    if constexpr (CT > 1) householder_block<KP, PLAIN, RBO, NWT, 1>(x, k, w, xcol, prow, part, slot, Gm, taus, cy);
+    if constexpr (CT > 2) householder_block<KP, PLAIN, RBO, NWT, 2>(x, k, w, xcol, prow, part, slot, Gm, taus, cy);
+    if constexpr (CT > 3) householder_block<KP, PLAIN, RBO, NWT, 3>(x, k, w, xcol, prow, part, slot, Gm, taus, cy);
+    // scale the Householder vectors: column c = 16 ct + l % 16 by its
+    // 1 / (alpha - beta) (0 for padding columns and tau = 0 columns, whose
+    // sub-columns are zero); the plain tile's rows <= c hold R
+    double sv[4];
+    gather_cols(cy.myscale, sv);
+    const int l = opaque_lane(), cl = l & 15;
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                if (PLAIN) {
+                    if (tile_row<RPW>(w, rb, l, v) > 16 * ct + cl) x[rb][ct][v] *= sv[ct];
+                } else {
+                    x[rb][ct][v] *= sv[ct];
+                }
+            }
+    return cy.beta_prev;
 }
 
 // T factor of the tile in TG (see leaf_chunk).  Diagonal 16 x 16 blocks by
