@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtho.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["k_small.hip", "k_tsqr.hip", "k_stream.hip", "k_lowp.hip", "k_batched.hip", "k_complex.hip", "tho_host.cpp", "tho_api.cpp", "tho_bcgs.cpp",
-           "tho_backward.cpp", "tho_batched.cpp", "tho_complex.cpp", "tho_noalloc.hip", "k_pchoice.hip", "k_checks.hip", "tho_block.cpp", "k_weighted.hip", "tho_weighted.cpp"]
+           "tho_backward.cpp", "tho_batched.cpp", "tho_complex.cpp", "tho_noalloc.hip", "k_pchoice.hip", "k_checks.hip", "tho_block.cpp", "k_weighted.hip", "tho_weighted.cpp", "k_zleaf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -83,11 +83,62 @@ std::vector<ZLevel> ztsqr_levels(const ZTsqrPlan& T, const dcplx* X, int64_t ldx
 
 // Householder QR of X (m x k) into explicit Q_ (in Y) and R (nonnegative
 // real diagonal); Y may equal X.
+// Optional V term of level 0 (Algorithm 1): the leaf factors A + V Z (Z in
+// B-operand order) and leaves M_c = Q_chunk^H V_chunk per chunk in Nc.
+struct ZFuse {
+    const dcplx* V = nullptr;
+    int64_t ldv = 0;
+    int k0 = 0, K0P = 0;
+    const dcplx* Zp = nullptr;
+    dcplx* Nc = nullptr;
+};
+
 int ztsqr(const ZTsqrPlan& T, const dcplx* X, int64_t ldx, dcplx* Y, int64_t ldy, dcplx* R, int64_t ldr,
-          hipStream_t st) {
+          hipStream_t st, const ZFuse* fz = nullptr, std::vector<ZLevel>* out_levels = nullptr) {
     std::vector<ZLevel> Ls = ztsqr_levels(T, X, ldx, Y, ldy);
     const int nl = (int)Ls.size();
-    for (int l = 0; l < nl; l++) PROF(l == 0 ? "zleaf_l0" : "zleaf_up", st, launch_zleaf(T.KP, Ls[l], st));
+    {
+        const ZLevel& z = Ls[0];
+        ZRLevel L0{};
+        L0.m = z.m;
+        L0.k = z.k;
+        L0.nchunk = z.nchunk;
+        L0.maxtiles = z.maxtiles;
+        L0.X = z.X;
+        L0.ldx = z.ldx;
+        L0.Y = z.Y;
+        L0.ldy = z.ldy;
+        L0.Tt = z.Tt;
+        L0.Rnext = z.Rnext;
+        L0.ldrn = z.ldrn;
+        int k0p = 0;
+        if (fz && fz->k0 > 0) {
+            L0.V = fz->V;
+            L0.ldv = fz->ldv;
+            L0.k0 = fz->k0;
+            L0.Zp = fz->Zp;
+            L0.Nc = fz->Nc;
+            k0p = fz->K0P;
+        }
+        PROF("zleaf_l0", st, launch_zleaf_rt(T.KP, k0p, L0, st));
+    }
+    for (int l = 1; l < nl; l++) {
+        const ZLevel& z = Ls[l];
+        ZRLevel Lu{};
+        Lu.m = z.m;
+        Lu.k = z.k;
+        Lu.nchunk = z.nchunk;
+        Lu.maxtiles = z.maxtiles;
+        Lu.X = z.X;
+        Lu.ldx = z.ldx;
+        Lu.Y = z.Y;
+        Lu.ldy = z.ldy;
+        Lu.Tt = z.Tt;
+        Lu.Rnext = z.Rnext;
+        Lu.ldrn = z.ldrn;
+        PROF("zleaf_up", st, launch_zleaf_rt(T.KP, 0, Lu, st));
+    }
+    if (out_levels) *out_levels = Ls;
     PROF("zfinish_r", st, launch_zfinish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
     for (int l = nl - 1; l >= 0; l--) PROF(l == 0 ? "zform_l0" : "zform_up", st, launch_zform(T.KP, Ls[l], st));
     return 0;
@@ -147,9 +198,11 @@ int zrows(const ZRows& Z, int64_t nrows, const dcplx* X, int64_t ldx, dcplx* Out
 
 struct ZPlan {
     ZTsqrPlan ts;
-    ZXty xa, xg;
-    ZRows rz, rn;
+    ZXty xa;
+    ZRows rn;
     dcplx *Pm, *Tm, *C, *Z, *A1t, *N;
+    dcplx *Zp, *Nc, *prod, *Gsum;  // fused level 0: permuted Z, chunk products, their reduction
+    int K0P;
     size_t bytes;
 };
 
@@ -157,10 +210,12 @@ void make_zplan(int64_t n, int64_t k0, int64_t k, void* ws, ZPlan& P) {
     Carve cv(ws);
     ztsqr_plan(n - k0, (int)k, cv, P.ts);
     P.Pm = P.Tm = P.C = P.Z = P.A1t = P.N = nullptr;
+    P.Zp = P.Nc = P.prod = P.Gsum = nullptr;
+    P.K0P = (int)k0p_of(k0);
     if (k0 > 0) {
+        const int KP = P.ts.KP, K0P = P.K0P;
+        const int nc0 = P.ts.lv[0].nchunk;
         zxty_plan(n, (int)k0, (int)k, cv, P.xa);
-        zxty_plan(n - k0, (int)k0, (int)k, cv, P.xg);
-        zrows_plan((int)k0, (int)k, cv, P.rz);
         zrows_plan((int)k0, (int)k, cv, P.rn);
         P.Pm = ztake(cv, (size_t)k0 * k0);
         P.Tm = ztake(cv, (size_t)k0 * k0);
@@ -168,6 +223,10 @@ void make_zplan(int64_t n, int64_t k0, int64_t k, void* ws, ZPlan& P) {
         P.Z = ztake(cv, (size_t)k0 * k);
         P.A1t = ztake(cv, (size_t)k0 * k);
         P.N = ztake(cv, (size_t)k0 * k);
+        P.Zp = ztake(cv, (size_t)(K0P / 4) * (KP / 16) * 64);
+        P.Nc = ztake(cv, (size_t)nc0 * KP * K0P);
+        P.prod = ztake(cv, (size_t)nc0 * K0P * KP);
+        P.Gsum = ztake(cv, (size_t)K0P * KP);
     }
     P.bytes = cv.bytes();
 }
@@ -213,17 +272,30 @@ int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.Z, k, 0, 1, 0, A, lda, P.A1t, k, st));
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, V, ldv, 0, P.Z, k, 0, 1, 0, P.A1t, k, P.A1t, k, st));
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, P.Pm, k0, 2, P.A1t, k, 0, 0, 0, nullptr, 0, S, lds, st));
-        // A1_low = A_low + V_low Z  (into the Q buffer)
-        if ((rc = zrows(P.rz, m, A + k0 * lda, lda, Q + k0 * ldq, ldq, V + k0 * ldv, ldv, ik0, P.Z, k, ik, 1.0, st)))
-            return rc;
-        X0 = Q + k0 * ldq;
-        ldx0 = ldq;
+        // Z in the B-operand order of the fused update A1_low = A_low + V_low Z
+        PROF("zpermute", st, launch_zpermute_b(P.K0P, P.ts.KP, ik0, ik, P.Z, k, P.Zp, st));
     }
-    // A1_low = Q_ R (Householder, chunked)
-    if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st))) return rc;
+    // A1_low = Q_ R (Householder, chunked; level 0 forms A1_low on the fly
+    // and the chunk products M_c = Q_chunk^H V_chunk)
+    ZFuse fz;
     if (k0 > 0) {
-        // G = W^H [0; Q_] = -V_low^H Q_ ;  N = T^{-1} G
-        if ((rc = zxty(P.xg, m, V + k0 * ldv, ldv, ik0, Q + k0 * ldq, ldq, ik, -1.0, P.N, k, st))) return rc;
+        fz.V = V + k0 * ldv;
+        fz.ldv = ldv;
+        fz.k0 = ik0;
+        fz.K0P = P.K0P;
+        fz.Zp = P.Zp;
+        fz.Nc = P.Nc;
+    }
+    std::vector<ZLevel> Ls;
+    if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st, k0 > 0 ? &fz : nullptr, &Ls))) return rc;
+    if (k0 > 0) {
+        // G = W^H [0; Q_] = -V_low^H Q_ = -sum_c M_c^H G_c ;  N = T^{-1} G
+        const int KP = P.ts.KP, K0P = P.K0P;
+        PROF("zchunk_prod", st, launch_zchunk_prod(Ls[0].nchunk, ik0, ik, KP, K0P, P.Nc, Ls[0].Gin, Ls[0].ldg,
+                                                   Ls[0].gstride, P.prod, st));
+        PROF("reduce_parts", st, launch_reduce_parts(Ls[0].nchunk, (int64_t)2 * K0P * KP, (const double*)P.prod,
+                                                     (double*)P.Gsum, st));
+        PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik, -1.0, P.Gsum, KP, 0, 0.0, nullptr, 0, 0, 0.0, 0, P.N, k, st));
         PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 0, P.N, k, st));
         // Q_low = Q_ + V_low N ;  Q_top = -(P - V_top) N
         if ((rc = zrows(P.rn, m, Q + k0 * ldq, ldq, Q + k0 * ldq, ldq, V + k0 * ldv, ldv, ik0, P.N, k, ik, 1.0, st)))

@@ -121,6 +121,31 @@ struct ZLevel {
 };
 int ztsqr_tile_rows(int kp);
 hipError_t launch_zleaf(int kp, const ZLevel& L, hipStream_t st);  // kp in {16, 32}
+// Level 0 of the complex chunked QR in registers (k_zleaf.hip) with the
+// update A + V Z fused in and the chunk products M_c = Q_chunk^H V_chunk
+// (KP x K0P each, into Nc); outputs as launch_zleaf.  k0p 0 (no V term), 16,
+// 32 or 64; tiles of zleaf_rt_tile_rows(kp) = ztsqr_tile_rows(kp) rows.
+struct ZRLevel {
+    int64_t m;
+    int k, k0, nchunk, maxtiles;
+    const dcplx* X;
+    int64_t ldx;
+    dcplx* Y;
+    int64_t ldy;
+    const dcplx* V;
+    int64_t ldv;
+    const dcplx* Zp;  // Z in B-operand order (launch_zpermute_b)
+    dcplx* Tt;
+    dcplx* Rnext;
+    int64_t ldrn;
+    dcplx* Nc;        // [nchunk][KP * K0P]
+};
+int zleaf_rt_tile_rows(int kp);
+hipError_t launch_zleaf_rt(int kp, int k0p, const ZRLevel& L, hipStream_t st);
+hipError_t launch_zpermute_b(int k0p, int kp, int k0, int k, const dcplx* Z, int64_t ldz, dcplx* out, hipStream_t st);
+// out_c = M_c^H G_c per chunk (k0p x kp complex each, zero-padded)
+hipError_t launch_zchunk_prod(int nchunk, int k0, int k, int kp, int k0p, const dcplx* M, const dcplx* G, int64_t ldg,
+                              int64_t gstride, dcplx* out, hipStream_t st);
 hipError_t launch_zform(int kp, const ZLevel& L, hipStream_t st);
 hipError_t launch_zqr_top(int n, const void* Vt, int64_t ldv, void* P, void* T, hipStream_t st);  // n <= 64
 // D = alpha op(A) op(B) + beta C (op: 0 none, 1 transpose, 2 conjugate transpose)
