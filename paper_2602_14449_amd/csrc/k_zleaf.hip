@@ -652,6 +652,215 @@ __global__ void k_zchunk_prod(int k0, int k, int kp, int k0p, const dcplx* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Formation of level 0 in two passes, as in the real path: per chunk the
+// k x k recurrence top-down (K_t = T_t C, C <- C - K_t for a structured
+// tile; K_0 = T_0 U_0[0:k]^H C for tile 0, whose top k rows also receive
+// C), with -K_t written over T_t in B-operand order and the final C into
+// Cfin; then every tile on its own: Q_t = [C; 0] (tile 0) - Y_t K_t + V_t N.
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_zkchain(ZLevel L, dcplx* Cfin) {
+    constexpr int LD = KP + 1, KS = KP / 4, CT = KP / 16;
+    constexpr int TB = ZGeo<KP>::TB;
+    extern __shared__ double sm[];
+    dcplx* Cs = (dcplx*)sm;    // KP x LD: the running C
+    dcplx* Es = Cs + KP * LD;  // KP x LD
+    dcplx* Ts = Es + KP * LD;  // KP x LD: T_t
+    const int tid = threadIdx.x, c = blockIdx.x, k = L.k;
+    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
+    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
+    const int ntiles = (int)((cr1 - cr0 + TB - 1) / TB);
+    {
+        const dcplx* G = L.Gin + (int64_t)c * L.gstride * L.ldg;
+        for (int e = tid; e < KP * KP; e += blockDim.x) {
+            const int i = e / KP, j = e % KP;
+            Cs[i * LD + j] = (i < k && j < k) ? G[(int64_t)i * L.ldg + j] : dcplx{0.0, 0.0};
+        }
+    }
+    const dcplx* Y0 = L.Y + cr0 * L.ldy;
+    for (int t = ntiles - 1; t >= 0; t--) {
+        const bool plain = (t == 0);
+        dcplx* Tt = L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP;
+        __syncthreads();
+        for (int e = tid; e < KP * KP; e += blockDim.x) Ts[(e / KP) * LD + e % KP] = Tt[e];
+        // E = U_0[0:k]^H C (tile 0) or C
+        for (int e = tid; e < KP * KP; e += blockDim.x) {
+            const int i = e / KP, j = e % KP;
+            double sr = 0.0, si = 0.0;
+            if (i < k && j < k) {
+                if (plain) {
+                    for (int p = 0; p < k; p++) {
+                        const dcplx a = Y0[(int64_t)p * L.ldy + i], b = Cs[p * LD + j];
+                        sr += a.re * b.re + a.im * b.im;
+                        si += a.re * b.im - a.im * b.re;
+                    }
+                } else {
+                    sr = Cs[i * LD + j].re;
+                    si = Cs[i * LD + j].im;
+                }
+            }
+            Es[i * LD + j] = dcplx{sr, si};
+        }
+        __syncthreads();
+        // K = T E (T upper triangular); -K over T_t in B-operand order
+        for (int e = tid; e < KP * KP; e += blockDim.x) {
+            const int i = e / KP, j = e % KP;
+            double sr = 0.0, si = 0.0;
+            if (i < k && j < k)
+                for (int p = i; p < k; p++) {
+                    const dcplx a = Ts[i * LD + p], b = Es[p * LD + j];
+                    sr += a.re * b.re - a.im * b.im;
+                    si += a.re * b.im + a.im * b.re;
+                }
+            Tt[((i % KS) * CT + j / 16) * 64 + 16 * (i / KS) + (j % 16)] = dcplx{-sr, -si};
+            if (!plain) Cs[i * LD + j] = dcplx{Cs[i * LD + j].re - sr, Cs[i * LD + j].im - si};
+        }
+    }
+    __syncthreads();
+    dcplx* Cf = Cfin + (int64_t)c * KP * KP;
+    for (int e = tid; e < KP * KP; e += blockDim.x) Cf[e] = Cs[(e / KP) * LD + e % KP];
+}
+
+// One workgroup per tile slot: Q_t = [C; 0] (tile 0) - Y_t K_t + V_t N on
+// MFMA (four real products per complex one), in place of Y_t; every
+// wavefront reads and writes only its own rows.
+template <int KP, int K0P>
+__global__ __launch_bounds__(ZNW * 64, 2) void k_zrows(ZLevel L, const dcplx* Cfin, const dcplx* V, int64_t ldv,
+                                                      int k0, const dcplx* Np) {
+    constexpr int RB = ZGeo<KP>::RB, RPW = ZGeo<KP>::RPW, TB = ZGeo<KP>::TB, CT = KP / 16, KS = KP / 4;
+    constexpr int KS0 = K0P > 0 ? K0P / 4 : 1;
+    const int c = blockIdx.x / L.maxtiles, t = blockIdx.x % L.maxtiles;
+    const int w = threadIdx.x >> 6, k = L.k;
+    const int64_t cr0 = (int64_t)c * L.m / L.nchunk;
+    const int64_t cr1 = (int64_t)(c + 1) * L.m / L.nchunk;
+    const int64_t r0 = cr0 + (int64_t)t * TB;
+    if (r0 >= cr1) return;  // slot beyond this chunk's tiles (uniform)
+    const int trows = (int)((cr1 - r0 < TB) ? (cr1 - r0) : TB);
+    const double* Kg = (const double*)(L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP);  // -K_t
+    double* Yt = (double*)(L.Y + r0 * L.ldy);
+    const int ldy = (int)L.ldy;
+    const int l = lane_id(), g = l >> 4, cl = l & 15;
+    d4 acr[RB][CT], aci[RB][CT];
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+            acr[rb][ct] = d4zero();
+            aci[rb][ct] = d4zero();
+        }
+    if (t == 0) {
+        const double* Cf = (const double*)(Cfin + (int64_t)c * KP * KP);
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int row = ztile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
+                    if (row < KP) {
+                        const double2 z = ld2(Cf + 2 * (row * KP + col));
+                        acr[rb][ct][v] = z.x;
+                        aci[rb][ct][v] = z.y;
+                    }
+                }
+    }
+    // - Y_t K_t (the stored -K_t), all KS K-steps' loads issued together
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++) {
+        const int yr = RPW * w + 16 * rb + cl;
+        double ar[KS], ai[KS];
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            double2 z = make_double2(0.0, 0.0);
+            if (yr < trows && g * KS + s < k) z = ld2(Yt + 2 * (yr * ldy + g * KS + s));
+            ar[s] = z.x;
+            ai[s] = z.y;
+        }
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+                const double2 b = ld2(Kg + 2 * ((s * CT + ct) * 64 + l));
+                acr[rb][ct] = mfma(ar[s], b.x, acr[rb][ct]);
+                acr[rb][ct] = mfma(-ai[s], b.y, acr[rb][ct]);
+                aci[rb][ct] = mfma(ar[s], b.y, aci[rb][ct]);
+                aci[rb][ct] = mfma(ai[s], b.x, aci[rb][ct]);
+            }
+    }
+    // + V_t N (N in B-operand order)
+    if (K0P > 0 && k0 > 0) {
+        const double* Vt = (const double*)(V + r0 * ldv);
+        constexpr int SC = 4;
+#pragma unroll 2
+        for (int s0 = 0; s0 < KS0; s0 += SC) {
+            double vr[RB][SC], vi[RB][SC], br[SC][CT], bi[SC][CT];
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++) {
+                const int xr = RPW * w + 16 * rb + cl;
+#pragma unroll
+                for (int s = 0; s < SC; s++) {
+                    const int kk = g * KS0 + s0 + s;
+                    double2 z = make_double2(0.0, 0.0);
+                    if (xr < trows && kk < k0) z = ld2(Vt + 2 * (xr * ldv + kk));
+                    vr[rb][s] = z.x;
+                    vi[rb][s] = z.y;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SC; s++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) {
+                    const double2 z = ld2((const double*)Np + 2 * (((s0 + s) * CT + ct) * 64 + l));
+                    br[s][ct] = z.x;
+                    bi[s][ct] = z.y;
+                }
+#pragma unroll
+            for (int s = 0; s < SC; s++)
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                    for (int ct = 0; ct < CT; ct++) {
+                        acr[rb][ct] = mfma(vr[rb][s], br[s][ct], acr[rb][ct]);
+                        acr[rb][ct] = mfma(-vi[rb][s], bi[s][ct], acr[rb][ct]);
+                        aci[rb][ct] = mfma(vr[rb][s], bi[s][ct], aci[rb][ct]);
+                        aci[rb][ct] = mfma(vi[rb][s], br[s][ct], aci[rb][ct]);
+                    }
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = ztile_row<RPW>(w, rb, l, v), col = 16 * ct + cl;
+                if (row < trows && col < k) st2(Yt + 2 * (row * ldy + col), acr[rb][ct][v], aci[rb][ct][v]);
+            }
+}
+
+template <int KP>
+hipError_t zkchain_t(const ZLevel& L, dcplx* Cfin, hipStream_t st) {
+    const size_t shm = 3 * KP * (KP + 1) * sizeof(dcplx);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_zkchain<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_zkchain<KP>), dim3(L.nchunk), dim3(256), shm, st, L, Cfin);
+    return hipGetLastError();
+}
+
+template <int KP, int K0P>
+hipError_t zrows_t(const ZLevel& L, const dcplx* Cfin, const dcplx* V, int64_t ldv, int k0, const dcplx* Np,
+                   hipStream_t st) {
+    hipLaunchKernelGGL((k_zrows<KP, K0P>), dim3((int64_t)L.nchunk * L.maxtiles), dim3(ZNW * 64), 0, st, L, Cfin, V,
+                       ldv, k0, Np);
+    return hipGetLastError();
+}
+
 template <int KP, int K0P>
 hipError_t zleaf_rt_t(const ZRLevel& L, hipStream_t st) {
     const size_t shm = ZLeafLds<KP>::total * sizeof(double);
@@ -681,6 +890,27 @@ hipError_t launch_zleaf_rt(int kp, int k0p, const ZRLevel& L, hipStream_t st) {
         case 32016: return zleaf_rt_t<32, 16>(L, st);
         case 32032: return zleaf_rt_t<32, 32>(L, st);
         case 32064: return zleaf_rt_t<32, 64>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zkchain(int kp, const ZLevel& L, dcplx* Cfin, hipStream_t st) {
+    if (kp == 16) return zkchain_t<16>(L, Cfin, st);
+    if (kp == 32) return zkchain_t<32>(L, Cfin, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zrows0(int kp, int k0p, const ZLevel& L, const dcplx* Cfin, const dcplx* V, int64_t ldv, int k0,
+                         const dcplx* Np, hipStream_t st) {
+    switch (kp * 1000 + k0p) {
+        case 16000: return zrows_t<16, 0>(L, Cfin, V, ldv, k0, Np, st);
+        case 16016: return zrows_t<16, 16>(L, Cfin, V, ldv, k0, Np, st);
+        case 16032: return zrows_t<16, 32>(L, Cfin, V, ldv, k0, Np, st);
+        case 16064: return zrows_t<16, 64>(L, Cfin, V, ldv, k0, Np, st);
+        case 32000: return zrows_t<32, 0>(L, Cfin, V, ldv, k0, Np, st);
+        case 32016: return zrows_t<32, 16>(L, Cfin, V, ldv, k0, Np, st);
+        case 32032: return zrows_t<32, 32>(L, Cfin, V, ldv, k0, Np, st);
+        case 32064: return zrows_t<32, 64>(L, Cfin, V, ldv, k0, Np, st);
         default: return hipErrorInvalidValue;
     }
 }

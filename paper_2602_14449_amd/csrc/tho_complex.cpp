@@ -94,7 +94,7 @@ struct ZFuse {
 };
 
 int ztsqr(const ZTsqrPlan& T, const dcplx* X, int64_t ldx, dcplx* Y, int64_t ldy, dcplx* R, int64_t ldr,
-          hipStream_t st, const ZFuse* fz = nullptr, std::vector<ZLevel>* out_levels = nullptr) {
+          hipStream_t st, const ZFuse* fz = nullptr, std::vector<ZLevel>* out_levels = nullptr, bool form0 = true) {
     std::vector<ZLevel> Ls = ztsqr_levels(T, X, ldx, Y, ldy);
     const int nl = (int)Ls.size();
     {
@@ -140,7 +140,8 @@ int ztsqr(const ZTsqrPlan& T, const dcplx* X, int64_t ldx, dcplx* Y, int64_t ldy
     }
     if (out_levels) *out_levels = Ls;
     PROF("zfinish_r", st, launch_zfinish_r(T.k, T.KP, T.Rtop, T.KP, R, ldr, T.G0, st));
-    for (int l = nl - 1; l >= 0; l--) PROF(l == 0 ? "zform_l0" : "zform_up", st, launch_zform(T.KP, Ls[l], st));
+    for (int l = nl - 1; l >= (form0 ? 0 : 1); l--)
+        PROF(l == 0 ? "zform_l0" : "zform_up", st, launch_zform(T.KP, Ls[l], st));
     return 0;
 }
 
@@ -199,9 +200,9 @@ int zrows(const ZRows& Z, int64_t nrows, const dcplx* X, int64_t ldx, dcplx* Out
 struct ZPlan {
     ZTsqrPlan ts;
     ZXty xa;
-    ZRows rn;
     dcplx *Pm, *Tm, *C, *Z, *A1t, *N;
     dcplx *Zp, *Nc, *prod, *Gsum;  // fused level 0: permuted Z, chunk products, their reduction
+    dcplx *Cfin, *Np;              // level-0 formation: final C per chunk, permuted N
     int K0P;
     size_t bytes;
 };
@@ -210,13 +211,12 @@ void make_zplan(int64_t n, int64_t k0, int64_t k, void* ws, ZPlan& P) {
     Carve cv(ws);
     ztsqr_plan(n - k0, (int)k, cv, P.ts);
     P.Pm = P.Tm = P.C = P.Z = P.A1t = P.N = nullptr;
-    P.Zp = P.Nc = P.prod = P.Gsum = nullptr;
+    P.Zp = P.Nc = P.prod = P.Gsum = P.Cfin = P.Np = nullptr;
     P.K0P = (int)k0p_of(k0);
     if (k0 > 0) {
         const int KP = P.ts.KP, K0P = P.K0P;
         const int nc0 = P.ts.lv[0].nchunk;
         zxty_plan(n, (int)k0, (int)k, cv, P.xa);
-        zrows_plan((int)k0, (int)k, cv, P.rn);
         P.Pm = ztake(cv, (size_t)k0 * k0);
         P.Tm = ztake(cv, (size_t)k0 * k0);
         P.C = ztake(cv, (size_t)k0 * k);
@@ -227,6 +227,8 @@ void make_zplan(int64_t n, int64_t k0, int64_t k, void* ws, ZPlan& P) {
         P.Nc = ztake(cv, (size_t)nc0 * KP * K0P);
         P.prod = ztake(cv, (size_t)nc0 * K0P * KP);
         P.Gsum = ztake(cv, (size_t)K0P * KP);
+        P.Cfin = ztake(cv, (size_t)nc0 * KP * KP);
+        P.Np = ztake(cv, (size_t)(K0P / 4) * (KP / 16) * 64);
     }
     P.bytes = cv.bytes();
 }
@@ -287,7 +289,7 @@ int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv
         fz.Nc = P.Nc;
     }
     std::vector<ZLevel> Ls;
-    if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st, k0 > 0 ? &fz : nullptr, &Ls))) return rc;
+    if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st, k0 > 0 ? &fz : nullptr, &Ls, k0 == 0))) return rc;
     if (k0 > 0) {
         // G = W^H [0; Q_] = -V_low^H Q_ = -sum_c M_c^H G_c ;  N = T^{-1} G
         const int KP = P.ts.KP, K0P = P.K0P;
@@ -297,9 +299,12 @@ int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv
                                                      (double*)P.Gsum, st));
         PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik, -1.0, P.Gsum, KP, 0, 0.0, nullptr, 0, 0, 0.0, 0, P.N, k, st));
         PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 0, P.N, k, st));
-        // Q_low = Q_ + V_low N ;  Q_top = -(P - V_top) N
-        if ((rc = zrows(P.rn, m, Q + k0 * ldq, ldq, Q + k0 * ldq, ldq, V + k0 * ldv, ldv, ik0, P.N, k, ik, 1.0, st)))
-            return rc;
+        // level 0 of the formation with Q_low = Q_ + V_low N in the same pass:
+        // the k x k recurrence per chunk, then every tile's rows
+        PROF("zkchain_l0", st, launch_zkchain(KP, Ls[0], P.Cfin, st));
+        PROF("zpermute", st, launch_zpermute_b(K0P, KP, ik0, ik, P.N, k, P.Np, st));
+        PROF("zrows_l0", st, launch_zrows0(KP, K0P, Ls[0], P.Cfin, V + k0 * ldv, ldv, ik0, P.Np, st));
+        // Q_top = -(P - V_top) N
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.N, k, 0, 0, 0, nullptr, 0, Q, ldq, st));
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, 1, 0, V, ldv, 0, P.N, k, 0, 1, 0, Q, ldq, Q, ldq, st));
     }

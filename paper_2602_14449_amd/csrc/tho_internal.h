@@ -143,6 +143,12 @@ struct ZRLevel {
 int zleaf_rt_tile_rows(int kp);
 hipError_t launch_zleaf_rt(int kp, int k0p, const ZRLevel& L, hipStream_t st);
 hipError_t launch_zpermute_b(int k0p, int kp, int k0, int k, const dcplx* Z, int64_t ldz, dcplx* out, hipStream_t st);
+// Two-pass formation of complex level 0: the per-chunk k x k recurrence
+// (overwrites each T_t with -K_t in B-operand order, fills Cfin), then every
+// tile's rows of Q = [C; 0] - Y_t K_t + V_t N (Np: N in B-operand order).
+hipError_t launch_zkchain(int kp, const ZLevel& L, dcplx* Cfin, hipStream_t st);
+hipError_t launch_zrows0(int kp, int k0p, const ZLevel& L, const dcplx* Cfin, const dcplx* V, int64_t ldv, int k0,
+                         const dcplx* Np, hipStream_t st);
 // out_c = M_c^H G_c per chunk (k0p x kp complex each, zero-padded)
 hipError_t launch_zchunk_prod(int nchunk, int k0, int k, int kp, int k0p, const dcplx* M, const dcplx* G, int64_t ldg,
                               int64_t gstride, dcplx* out, hipStream_t st);
