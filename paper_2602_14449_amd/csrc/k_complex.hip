@@ -323,10 +323,19 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
         const cplx tau = sc[0], scl = sc[1];
         for (int i = j + 1 + tid; i < n; i += CW) M[i * ld + j] = cmul(M[i * ld + j], scl);
         __syncthreads();
-        for (int cc = j + 1 + tid; cc < n; cc += CW) {
-            cplx s = M[j * ld + cc];
-            for (int i = j + 1; i < n; i++) s = cadd(s, cmulc(M[i * ld + j], M[i * ld + cc]));
-            wv[cc] = s;
+        {
+            // four lanes (a quad) per column, each over every fourth row
+            const int cc = j + 1 + (tid >> 2), q = tid & 3;
+            double sr = 0.0, si = 0.0;
+            if (cc < n)
+                for (int i = j + 1 + q; i < n; i += 4) {
+                    const cplx a = M[i * ld + j], b = M[i * ld + cc];
+                    sr += a.re * b.re + a.im * b.im;
+                    si += a.re * b.im - a.im * b.re;
+                }
+            sr = sum_quad(sr);
+            si = sum_quad(si);
+            if (cc < n && q == 0) wv[cc] = cadd(M[j * ld + cc], cmk(sr, si));
         }
         __syncthreads();
         const cplx tc = cconj(tau);
@@ -354,10 +363,19 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
     for (int j = n - 1; j >= 0; j--) {
         const cplx tau = taus[j];
         if (j < n - 1) {
-            for (int cc = j + 1 + tid; cc < n; cc += CW) {
-                cplx s = cmk(0.0, 0.0);  // row j of a formed column c > j is zero
-                for (int i = j + 1; i < n; i++) s = cadd(s, cmulc(M[i * ld + j], M[i * ld + cc]));
-                wv[cc] = s;
+            {
+                // row j of a formed column c > j is zero; a quad per column
+                const int cc = j + 1 + (tid >> 2), q = tid & 3;
+                double sr = 0.0, si = 0.0;
+                if (cc < n)
+                    for (int i = j + 1 + q; i < n; i += 4) {
+                        const cplx a = M[i * ld + j], b = M[i * ld + cc];
+                        sr += a.re * b.re + a.im * b.im;
+                        si += a.re * b.im - a.im * b.re;
+                    }
+                sr = sum_quad(sr);
+                si = sum_quad(si);
+                if (cc < n && q == 0) wv[cc] = cmk(sr, si);
             }
             __syncthreads();
             for (int e = tid; e < (n - j) * (n - j - 1); e += CW) {

@@ -291,18 +291,25 @@ int run_ztwo_stage(int64_t n, int64_t k0, int64_t k, const dcplx* V, int64_t ldv
     std::vector<ZLevel> Ls;
     if ((rc = ztsqr(P.ts, X0, ldx0, Q + k0 * ldq, ldq, R, ldr, st, k0 > 0 ? &fz : nullptr, &Ls, k0 == 0))) return rc;
     if (k0 > 0) {
-        // G = W^H [0; Q_] = -V_low^H Q_ = -sum_c M_c^H G_c ;  N = T^{-1} G
+        // G = W^H [0; Q_] = -V_low^H Q_ = -sum_c M_c^H G_c ;  N = T^{-1} G.
+        // The k x k recurrence of the level-0 formation needs neither: it
+        // runs on the side stream meanwhile.
         const int KP = P.ts.KP, K0P = P.K0P;
+        Fork& f = fork_for_thread();
+        if (!f.ok) return set_err(THO_E_HIP, "could not create the side stream");
+        HIPCHK(hipEventRecord(f.ev0, st));
+        HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
+        PROF("zkchain_l0", f.side, launch_zkchain(KP, Ls[0], P.Cfin, f.side));
+        HIPCHK(hipEventRecord(f.ev1, f.side));
         PROF("zchunk_prod", st, launch_zchunk_prod(Ls[0].nchunk, ik0, ik, KP, K0P, P.Nc, Ls[0].Gin, Ls[0].ldg,
                                                    Ls[0].gstride, P.prod, st));
         PROF("reduce_parts", st, launch_reduce_parts(Ls[0].nchunk, (int64_t)2 * K0P * KP, (const double*)P.prod,
                                                      (double*)P.Gsum, st));
         PROF("zsmall_ew", st, launch_zsmall_ew(ik0, ik, -1.0, P.Gsum, KP, 0, 0.0, nullptr, 0, 0, 0.0, 0, P.N, k, st));
         PROF("ztrsm", st, launch_ztrsm(ik0, ik, P.Tm, k0, 0, P.N, k, st));
-        // level 0 of the formation with Q_low = Q_ + V_low N in the same pass:
-        // the k x k recurrence per chunk, then every tile's rows
-        PROF("zkchain_l0", st, launch_zkchain(KP, Ls[0], P.Cfin, st));
+        // level 0 of the formation with Q_low = Q_ + V_low N in the same pass
         PROF("zpermute", st, launch_zpermute_b(K0P, KP, ik0, ik, P.N, k, P.Np, st));
+        HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
         PROF("zrows_l0", st, launch_zrows0(KP, K0P, Ls[0], P.Cfin, V + k0 * ldv, ldv, ik0, P.Np, st));
         // Q_top = -(P - V_top) N
         PROF("zgemm", st, launch_zgemm(ik0, ik, ik0, -1, 0, P.Pm, k0, 0, P.N, k, 0, 0, 0, nullptr, 0, Q, ldq, st));
