@@ -1023,6 +1023,40 @@ __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __res
     }
 }
 
+// rows_prod for a full tile (every row present, kmax = 4 KS) with X 16-byte
+// aligned and ldx even: no masks, so each lane's KS-long row piece is read
+// with 16-byte loads.
+template <int RB, int CT, int KS>
+__device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
+                                               const double* __restrict__ B, int l) {
+    constexpr int SC = (KS < 8) ? KS : 8;
+    const int g = l >> 4, cl = l & 15;
+#pragma unroll 2
+    for (int s0 = 0; s0 < KS; s0 += SC) {
+        double a[RB][SC], b[SC][CT];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const double2* xp = (const double2*)(X + (row0 + 16 * rb + cl) * ldx + g * KS + s0);
+#pragma unroll
+            for (int s = 0; s < SC / 2; s++) {
+                const double2 z = xp[s];
+                a[rb][2 * s] = z.x;
+                a[rb][2 * s + 1] = z.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
+    }
+}
+
 template <int KP, int K0P, int PANEL>
 __device__ __forceinline__ void rows_tile(const TsqrLevel& L, const int c, const int t) {
     constexpr int RB = Geo<KP>::RB, RPW = Geo<KP>::RPW, TB = Geo<KP>::TB;
@@ -1063,9 +1097,28 @@ __device__ __forceinline__ void rows_tile(const TsqrLevel& L, const int c, const
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) acc[rb][ct] = d4zero();
     }
+    // a full tile with 16-byte aligned rows takes the unmasked paths
+    const bool full = trows == TB && k == KP && (!HASV || k0 == K0P) && ((ldy | (HASV ? ldv : 0)) & 1) == 0 &&
+                      ((((uintptr_t)Yt) | ((uintptr_t)Vt)) & 15) == 0;
     // - Y_t K_t: all KSK K-steps at once (the loads of Y and of K_t are
     // issued together, deepest memory-level parallelism)
-    {
+    if (full) {
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const double2* yp = (const double2*)(Yt + (RPW * w + 16 * rb + cl) * ldy + g * KSK);
+            double a[KSK];
+#pragma unroll
+            for (int s = 0; s < KSK / 2; s++) {
+                const double2 z = yp[s];
+                a[2 * s] = z.x;
+                a[2 * s + 1] = z.y;
+            }
+#pragma unroll
+            for (int s = 0; s < KSK; s++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[s], Kg[(s * CT + ct) * 64 + l], acc[rb][ct]);
+        }
+    } else {
         const int g = l >> 4, cl = l & 15;
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
@@ -1081,7 +1134,10 @@ __device__ __forceinline__ void rows_tile(const TsqrLevel& L, const int c, const
         }
     }
     // + V_t N (N in B-operand order, see k_permute_b)
-    if (PANEL == PANEL_F64 && HASV && k0 > 0) rows_prod<RB, CT, KS0>(acc, Vt, ldv, RPW * w, trows, k0, L.Nglob, l);
+    if (PANEL == PANEL_F64 && HASV && k0 > 0) {
+        if (full) rows_prod_full<RB, CT, KS0>(acc, Vt, ldv, RPW * w, L.Nglob, l);
+        else rows_prod<RB, CT, KS0>(acc, Vt, ldv, RPW * w, trows, k0, L.Nglob, l);
+    }
     if (PANEL != PANEL_F64 && HASV && k0 > 0)
         vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(acc, Vt, ldv, RPW * w, trows, k0, L.Nlp, l);
     // each wavefront reads and writes only its own rows: no barrier
