@@ -33,16 +33,22 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
     const int c = tid % CW, rg = tid / CW;  // column, row group
     for (int e = tid; e < n * n; e += blockDim.x) M[(e / n) * ld + (e % n)] = Vt[(int64_t)(e / n) * ldv + (e % n)];
     __syncthreads();
+    // Two workgroup barriers per column.  Thread (c, rg) forms the partial
+    // dot d_c = sum over its rows i > j of x_ij x_ic for every c >= j (c = j
+    // gives sigma^2); after the barrier every thread builds the reflector
+    // from sigma^2 and alpha = M[j][j] itself, and the threads of column c > j
+    // apply it: w_c = M[j][c] + s d_c with u = [1; s x_sub], s = 1 / (alpha -
+    // beta).  Column j is scaled after the second barrier; no later step of
+    // the factorization reads it.
     for (int j = 0; j < n; j++) {
-        // sum of squares of the subcolumn below the pivot
-        double ss = 0.0;
-        if (tid < 64) {
-            for (int i = j + 1 + tid; i < n; i += 64) ss += M[i * ld + j] * M[i * ld + j];
-            ss = sum_wave(ss);
-            if (tid == 0) red[0] = ss;
+        if (c < n && c >= j) {
+            double s = 0.0;
+            for (int i = j + 1 + rg; i < n; i += RG) s += M[i * ld + j] * M[i * ld + c];
+            part[rg * n + c] = s;
         }
         __syncthreads();
-        const double sig2 = red[0];
+        double sig2 = 0.0;
+        for (int r = 0; r < RG; r++) sig2 += part[r * n + j];
         const double alpha = M[j * ld + j];
         double beta = alpha, tau = 0.0, scale = 0.0;
         if (sig2 != 0.0) {
@@ -51,30 +57,27 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
             tau = (beta - alpha) / beta;
             scale = 1.0 / (alpha - beta);
         }
-        __syncthreads();  // everyone has read M[j][j] and red
+        // (every thread of column c reads the pivot-row entry M[j][c]; the
+        // updated entry is stored after the barrier)
+        double rowj = 0.0;
+        if (c < n && c > j) {
+            double d = 0.0;
+            for (int r = 0; r < RG; r++) d += part[r * n + c];
+            rowj = M[j * ld + c];
+            const double tw = tau * (rowj + scale * d);
+            const double tws = tw * scale;
+            rowj -= tw;
+            for (int i = j + 1 + rg; i < n; i += RG) M[i * ld + c] -= tws * M[i * ld + j];
+        }
+        __syncthreads();
+        if (c < n && c > j && rg == 0) M[j * ld + c] = rowj;
         if (tid > j && tid < n) M[tid * ld + j] *= scale;
-        if (tid == 0) { taus[j] = tau; M[j * ld + j] = beta; }
-        __syncthreads();
-        // w_c = M[j][c] + sum_{i>j} v_i M[i][c] for c > j
-        if (c < n && c > j) {
-            double s = 0.0;
-            for (int i = j + 1 + rg; i < n; i += RG) s += M[i * ld + j] * M[i * ld + c];
-            part[rg * n + c] = s;
+        if (tid == 0) {
+            taus[j] = tau;
+            M[j * ld + j] = beta;
         }
-        __syncthreads();
-        if (tid < n && tid > j) {
-            double s = M[j * ld + tid];
-            for (int r = 0; r < RG; r++) s += part[r * n + tid];
-            wv[tid] = s;
-        }
-        __syncthreads();
-        if (c < n && c > j) {
-            const double tw = tau * wv[c];
-            if (rg == 0) M[j * ld + c] -= tw;
-            for (int i = j + 1 + rg; i < n; i += RG) M[i * ld + c] -= tw * M[i * ld + j];
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // R1 diagonal signs and T = I + D R1^T (rows of R scaled by d)
     for (int e = tid; e < n * n; e += blockDim.x) {
         const int i = e / n, jj = e % n;  // T[i][jj] = delta + d_jj R[jj][i] for jj <= i
@@ -98,19 +101,20 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
                 part[rg * n + c] = s;
             }
             __syncthreads();
-            if (tid < n && tid > j) {
-                // row j of an already formed column c > j is zero
-                double s = M[j * ld + tid];
-                for (int r = 0; r < RG; r++) s += part[r * n + tid];
-                wv[tid] = s;
-            }
-            __syncthreads();
+            double rowj = 0.0;
             if (c < n && c > j) {
-                const double tw = tau * wv[c];
-                if (rg == 0) M[j * ld + c] -= tw;
+                // row j of an already formed column c > j is zero; its
+                // update is stored after the barrier (every thread of the
+                // column reads it first)
+                rowj = M[j * ld + c];
+                double wc = rowj;
+                for (int r = 0; r < RG; r++) wc += part[r * n + c];
+                const double tw = tau * wc;
+                rowj -= tw;
                 for (int i = j + 1 + rg; i < n; i += RG) M[i * ld + c] -= tw * M[i * ld + j];
             }
             __syncthreads();
+            if (c < n && c > j && rg == 0) M[j * ld + c] = rowj;
         }
         if (tid < n) {
             if (tid > j) M[tid * ld + j] = -tau * M[tid * ld + j];
