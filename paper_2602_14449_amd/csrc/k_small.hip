@@ -18,7 +18,7 @@ namespace tho {
 // Output: part[blk][16*MT][16*NT], row-major.
 // --------------------------------------------------------------------------
 template <int MT, int NT, int WM>
-__global__ __launch_bounds__(256) void k_xty_partial(
+__global__ __launch_bounds__(256, 3) void k_xty_partial(
     int64_t nrows, const double* __restrict__ X, int64_t ldx, int p,
     const double* __restrict__ Y, int64_t ldy, int q, int64_t rows_per_blk,
     double* __restrict__ part) {

@@ -216,10 +216,11 @@ int tsqr_form0(const TsqrPlan& T, std::vector<TsqrLevel>& Ls, int k0p, hipStream
     return tsqr_rows0(T, Ls, k0p, st, panel);
 }
 
-// about four workgroups per compute unit, >= 64 rows each
+// two workgroups per compute unit, >= 64 rows each (all resident at once,
+// with room left beside them for the one-workgroup QR of the top block)
 XtyPlan xty_plan(int64_t nrows) {
     XtyPlan xp;
-    int64_t nb = std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(nrows, 64)));
+    int64_t nb = std::max<int64_t>(1, std::min<int64_t>(512, cdiv(nrows, 64)));
     xp.rows_per_blk = std::max<int64_t>(16, cdiv(cdiv(nrows, nb), 16) * 16);
     xp.nblk = (int)std::max<int64_t>(1, cdiv(nrows, xp.rows_per_blk));
     return xp;
