@@ -432,44 +432,90 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zleaf_rt(ZRLevel L) {
                         if (row < trows && col < k) st2(Yt + 2 * (row * ldy + col), xr[rb][ct][v], xi[rb][ct][v]);
                     }
         }
-        // T factor: row r of T by the recurrence T(r, r) = tau_r,
-        // T(r, i) = -tau_i sum_{r <= p < i} T(r, p) G(p, i); one thread per row
-        if (tid < k) {
-            double Trr[KP], Tri[KP];
-            const int r = tid;
+        // T factor (H_0 ... H_{k-1} = I - U T U^H) in 16 x 16 blocks: each
+        // diagonal block by the recurrence T(r, r) = tau_r,
+        // T(r, i) = -tau_i sum_{r <= p < i} T(r, p) G(p, i) within the block
+        // (one thread per row, the blocks in parallel); then, for KP = 32,
+        // the off-diagonal block X = -T_a (U_a^H U_b) T_b of the product of
+        // the two blocks' transformations
+        if (tid < KP) {
+            const int r = tid, b0 = (r / 16) * 16;
+            double Trr[16], Tri[16];  // T(r, b0 + jj)
 #pragma unroll
-            for (int jj = 0; jj < KP; jj++) {
-                Trr[jj] = (jj == r) ? S.tar[r] : 0.0;
-                Tri[jj] = (jj == r) ? S.tai[r] : 0.0;
+            for (int jj = 0; jj < 16; jj++) {
+                Trr[jj] = (b0 + jj == r && r < k) ? S.tar[r] : 0.0;
+                Tri[jj] = (b0 + jj == r && r < k) ? S.tai[r] : 0.0;
             }
 #pragma unroll
-            for (int i = 1; i < KP; i++) {
+            for (int ii = 1; ii < 16; ii++) {
+                const int i = b0 + ii;
                 if (i > r && i < k) {
                     double sr2 = 0.0, si2 = 0.0;
 #pragma unroll
-                    for (int p = 0; p < i; p++)
-                        if (p >= r) {
-                            const double gr = S.gr[i * LDT + p], gi = S.gi[i * LDT + p];
-                            sr2 += Trr[p] * gr - Tri[p] * gi;
-                            si2 += Trr[p] * gi + Tri[p] * gr;
+                    for (int pp = 0; pp < ii; pp++)
+                        if (b0 + pp >= r) {
+                            const double gr = S.gr[i * LDT + b0 + pp], gi = S.gi[i * LDT + b0 + pp];
+                            sr2 += Trr[pp] * gr - Tri[pp] * gi;
+                            si2 += Trr[pp] * gi + Tri[pp] * gr;
                         }
                     const double tr = S.tar[i], ti = S.tai[i];
-                    Trr[i] = -(tr * sr2 - ti * si2);
-                    Tri[i] = -(tr * si2 + ti * sr2);
+                    Trr[ii] = -(tr * sr2 - ti * si2);
+                    Tri[ii] = -(tr * si2 + ti * sr2);
                 }
             }
-            double* Tg = (double*)(L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP);
 #pragma unroll
-            for (int jj = 0; jj < KP; jj++) {
-                const double a = jj < k ? Trr[jj] : 0.0, b = jj < k ? Tri[jj] : 0.0;
-                st2(Tg + 2 * (r * KP + jj), a, b);
-                S.tlr[r * LDT + jj] = a;
-                S.tli[r * LDT + jj] = b;
+            for (int jj = 0; jj < 16; jj++) {
+                S.tlr[r * LDT + b0 + jj] = Trr[jj];
+                S.tli[r * LDT + b0 + jj] = Tri[jj];
             }
-        } else if (tid < KP) {
-            for (int jj = 0; jj < KP; jj++) {
-                S.tlr[tid * LDT + jj] = 0.0;
-                S.tli[tid * LDT + jj] = 0.0;
+            if constexpr (KP == 32) {
+                // the other block of row r: zero below the diagonal blocks
+                // (block b, row r >= 16); block a rows are overwritten by X
+                const int o0 = 16 - b0;
+#pragma unroll
+                for (int jj = 0; jj < 16; jj++) {
+                    S.tlr[r * LDT + o0 + jj] = 0.0;
+                    S.tli[r * LDT + o0 + jj] = 0.0;
+                }
+            }
+        }
+        if constexpr (KP == 32) {
+            __syncthreads();
+            // Y1 = G_ab T_b (16 x 16), G(p, q) at [q][p]; kept in the unused
+            // upper part of the Gram array, Y1(p, i) at [p][i] (p < 16 <= i)
+            {
+                const int p = tid >> 4, i = 16 + (tid & 15);
+                double yr = 0.0, yi = 0.0;
+                for (int q = 16; q <= i; q++) {
+                    const double gr = S.gr[q * LDT + p], gi = S.gi[q * LDT + p];
+                    const double tr = S.tlr[q * LDT + i], ti = S.tli[q * LDT + i];
+                    yr += gr * tr - gi * ti;
+                    yi += gr * ti + gi * tr;
+                }
+                S.gr[p * LDT + i] = yr;
+                S.gi[p * LDT + i] = yi;
+            }
+            __syncthreads();
+            // X(r, i) = -sum_{r <= p < 16} T_a(r, p) Y1(p, i)
+            {
+                const int r = tid >> 4, i = 16 + (tid & 15);
+                double xr2 = 0.0, xi2 = 0.0;
+                for (int p = r; p < 16; p++) {
+                    const double tr = S.tlr[r * LDT + p], ti = S.tli[r * LDT + p];
+                    const double yr = S.gr[p * LDT + i], yi = S.gi[p * LDT + i];
+                    xr2 += tr * yr - ti * yi;
+                    xi2 += tr * yi + ti * yr;
+                }
+                S.tlr[r * LDT + i] = (r < k && i < k) ? -xr2 : 0.0;
+                S.tli[r * LDT + i] = (r < k && i < k) ? -xi2 : 0.0;
+            }
+        }
+        __syncthreads();
+        {
+            double* Tg = (double*)(L.Tt + ((int64_t)c * L.maxtiles + t) * KP * KP);
+            for (int e = tid; e < KP * KP; e += blockDim.x) {
+                const int r = e / KP, jj = e % KP;
+                st2(Tg + 2 * e, S.tlr[r * LDT + jj], S.tli[r * LDT + jj]);
             }
         }
         __syncthreads();  // T is in LDS; every read of the Gram is done
