@@ -306,46 +306,49 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
     const int tid = threadIdx.x;
     for (int e = tid; e < n * n; e += CW) M[(e / n) * ld + e % n] = Vt[(int64_t)(e / n) * ldv + e % n];
     __syncthreads();
+    // Two workgroup barriers per column: a quad of lanes per column c >= j
+    // forms d_c = sum_{i > j} conj(x_ij) x_ic (c = j gives sigma^2); after the
+    // barrier every thread builds the reflector itself and the quads of the
+    // columns c > j apply it, w_c = M[j][c] + conj(s) d_c with u = [1; s x_sub];
+    // the pivot-row entries and the scaled column j are stored after the
+    // second barrier (no later step of the factorization reads them before).
     for (int j = 0; j < n; j++) {
-        double ss = 0.0;
-        for (int i = j + 1 + tid; i < n; i += CW) ss += cabs2(M[i * ld + j]);
-        ss = wg_sum(ss, red);
+        const int cc = j + (tid >> 2), q = tid & 3;
+        double dr = 0.0, di = 0.0;
+        if (cc < n)
+            for (int i = j + 1 + q; i < n; i += 4) {
+                const cplx a = M[i * ld + j], b = M[i * ld + cc];
+                dr += a.re * b.re + a.im * b.im;
+                di += a.re * b.im - a.im * b.re;
+            }
+        dr = sum_quad(dr);
+        di = sum_quad(di);
+        if (cc < n && q == 0) wv[cc] = cmk(dr, di);
+        __syncthreads();
+        const cplx alpha = M[j * ld + j];
+        double beta;
+        cplx tau, scl;
+        make_reflector(alpha, wv[j].re, beta, tau, scl);
+        cplx rowj = cmk(0.0, 0.0);
+        if (cc > j && cc < n) {
+            const cplx d = wv[cc];
+            rowj = M[j * ld + cc];
+            // w = p + conj(s) d ; the column takes -conj(tau) w u
+            const cplx w = cadd(rowj, cmulc(scl, d));
+            const cplx tw = cmul(cconj(tau), w);
+            const cplx tws = cmul(tw, scl);
+            rowj = csub(rowj, tw);
+            for (int i = j + 1 + q; i < n; i += 4) M[i * ld + cc] = csub(M[i * ld + cc], cmul(M[i * ld + j], tws));
+        }
+        __syncthreads();
+        if (cc > j && cc < n && q == 0) M[j * ld + cc] = rowj;
+        for (int i = j + 1 + tid; i < n; i += CW) M[i * ld + j] = cmul(M[i * ld + j], scl);
         if (tid == 0) {
-            double beta;
-            cplx tau, scl;
-            make_reflector(M[j * ld + j], ss, beta, tau, scl);
-            sc[0] = tau;
-            sc[1] = scl;
             taus[j] = tau;
             M[j * ld + j] = cmk(beta, 0.0);
         }
-        __syncthreads();
-        const cplx tau = sc[0], scl = sc[1];
-        for (int i = j + 1 + tid; i < n; i += CW) M[i * ld + j] = cmul(M[i * ld + j], scl);
-        __syncthreads();
-        {
-            // four lanes (a quad) per column, each over every fourth row
-            const int cc = j + 1 + (tid >> 2), q = tid & 3;
-            double sr = 0.0, si = 0.0;
-            if (cc < n)
-                for (int i = j + 1 + q; i < n; i += 4) {
-                    const cplx a = M[i * ld + j], b = M[i * ld + cc];
-                    sr += a.re * b.re + a.im * b.im;
-                    si += a.re * b.im - a.im * b.re;
-                }
-            sr = sum_quad(sr);
-            si = sum_quad(si);
-            if (cc < n && q == 0) wv[cc] = cadd(M[j * ld + cc], cmk(sr, si));
-        }
-        __syncthreads();
-        const cplx tc = cconj(tau);
-        for (int e = tid; e < (n - j) * (n - j - 1); e += CW) {
-            const int i = j + e / (n - j - 1), cc = j + 1 + e % (n - j - 1);
-            const cplx u = (i == j) ? cmk(1.0, 0.0) : M[i * ld + j];
-            M[i * ld + cc] = csub(M[i * ld + cc], cmul(u, cmul(tc, wv[cc])));
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // T = I + D R^H (lower), D = sign(diag R) real; keep the signs
     for (int e = tid; e < n * n; e += CW) {
         const int i = e / n, jj = e % n;

@@ -678,19 +678,28 @@ __global__ void k_zpermute_b(int k0p, int kp, int k0, int k, const dcplx* __rest
 
 // Per chunk, out_c = M_c^H G_c (k0 x k complex, ld kp): M_c the chunk's
 // Q_chunk^H V_chunk (KP x K0P), G_c the chunk's block of the formed Q of the
-// level above (rows c * gstride .., ld ldg).
+// level above (rows c * gstride .., ld ldg); both staged through LDS.
 __global__ void k_zchunk_prod(int k0, int k, int kp, int k0p, const dcplx* __restrict__ M,
                               const dcplx* __restrict__ G, int64_t ldg, int64_t gstride, dcplx* out) {
+    extern __shared__ double sm[];
+    dcplx* Ms = (dcplx*)sm;   // kp x k0p
+    dcplx* Gs = Ms + kp * k0p;  // kp x kp
     const int c = blockIdx.x;
     const dcplx* Mc = M + (int64_t)c * kp * k0p;
     const dcplx* Gc = G + (int64_t)c * gstride * ldg;
     dcplx* Oc = out + (int64_t)c * k0p * kp;
+    for (int e = threadIdx.x; e < kp * k0p; e += blockDim.x) Ms[e] = Mc[e];
+    for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
+        const int p = e / kp, j = e % kp;
+        Gs[e] = (p < k && j < k) ? Gc[(int64_t)p * ldg + j] : dcplx{0.0, 0.0};
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < k0p * kp; e += blockDim.x) {
         const int i = e / kp, j = e % kp;
         double sr = 0.0, si = 0.0;
         if (i < k0 && j < k)
             for (int p = 0; p < k; p++) {
-                const dcplx a = Mc[(int64_t)p * k0p + i], b = Gc[(int64_t)p * ldg + j];
+                const dcplx a = Ms[p * k0p + i], b = Gs[p * kp + j];
                 sr += a.re * b.re + a.im * b.im;  // conj(a) b
                 si += a.re * b.im - a.im * b.re;
             }
@@ -969,7 +978,8 @@ hipError_t launch_zpermute_b(int k0p, int kp, int k0, int k, const dcplx* Z, int
 
 hipError_t launch_zchunk_prod(int nchunk, int k0, int k, int kp, int k0p, const dcplx* M, const dcplx* G, int64_t ldg,
                               int64_t gstride, dcplx* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_zchunk_prod, dim3(nchunk), dim3(256), 0, st, k0, k, kp, k0p, M, G, ldg, gstride, out);
+    const size_t shm = (size_t)(kp * k0p + kp * kp) * sizeof(dcplx);
+    hipLaunchKernelGGL(k_zchunk_prod, dim3(nchunk), dim3(256), shm, st, k0, k, kp, k0p, M, G, ldg, gstride, out);
     return hipGetLastError();
 }
 
