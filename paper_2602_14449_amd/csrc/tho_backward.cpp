@@ -260,16 +260,21 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
     PROF("pack_b", st, launch_pack_b(ik, ik0, P.N, KP, 1, 1.0, KP, QP0, P.pk[0], st));
     PROF("pack_b", st, launch_pack_b(ik, ik0, P.Z, KP, 1, 1.0, KP, QP0, P.pk[1], st));
     PROF("pack_b", st, launch_pack_b(ik, ik0, P.Yb, KP, 1, -1.0, KP, QP0, P.pk[2], st));
+    PROF("pack_b", st, launch_pack_b(ik, ik0, P.Gb, KP, 1, -1.0, KP, QP0, P.pk[3], st));
+    // the top k0 rows take three terms, the bottom rows also - Q_ G_bar^T
+    // (one pass over them)
     {
-        RowsGemm g = rows(n, nullptr, 0, dV, lddv, ik0);
+        RowsGemm g = rows(k0, nullptr, 0, dV, lddv, ik0);
         add_term(g, gQ, ldgq, ik, KP, P.pk[0]);
         add_term(g, dA, ldda, ik, KP, P.pk[1]);
         add_term(g, A, lda, ik, KP, P.pk[2]);
         PROF("rows_gemm", st, launch_rows_gemm(g, st));
     }
-    PROF("pack_b", st, launch_pack_b(ik, ik0, P.Gb, KP, 1, -1.0, KP, QP0, P.pk[3], st));
     {
-        RowsGemm g = rows(m, dV + k0 * lddv, lddv, dV + k0 * lddv, lddv, ik0);
+        RowsGemm g = rows(m, nullptr, 0, dV + k0 * lddv, lddv, ik0);
+        add_term(g, gQ + k0 * ldgq, ldgq, ik, KP, P.pk[0]);
+        add_term(g, dA + k0 * ldda, ldda, ik, KP, P.pk[1]);
+        add_term(g, A + k0 * lda, lda, ik, KP, P.pk[2]);
         add_term(g, P.Qu, k, ik, KP, P.pk[3]);
         PROF("rows_gemm", st, launch_rows_gemm(g, st));
     }
