@@ -106,6 +106,94 @@ __global__ __launch_bounds__(256, 3) void k_xty_partial(
     }
 }
 
+// part[blk] = X[r0:r1]^T [Y0 Y1 Y2][r0:r1] for three matrices of q columns
+// each (the adjoint's V^T [A, Q, G_Q]), read in one pass over X: output
+// (16 MT) x (3 * 16 NB) row-major, the blocks of Y_i side by side.  Same
+// structure as k_xty_partial with WM = MT wave groups over the row tiles.
+template <int MT, int NB>
+__global__ __launch_bounds__(256, 2) void k_xty3_partial(int64_t nrows, const double* __restrict__ X, int64_t ldx,
+                                                         int p, const double* __restrict__ Y0, int64_t ld0,
+                                                         const double* __restrict__ Y1, int64_t ld1,
+                                                         const double* __restrict__ Y2, int64_t ld2, int q,
+                                                         int64_t rows_per_blk, double* __restrict__ part) {
+    constexpr int WM = (MT >= 4) ? 4 : MT;
+    constexpr int MTW = MT / WM;
+    constexpr int WR = 4 / WM;
+    constexpr int NT = 3 * NB;
+    constexpr int RED = (WR > 1) ? (WR - 1) * WM * MTW * NT * 64 : 1;
+    __shared__ d4 red[RED];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w % WM, wr = w / WM;
+    const int g = l >> 4, cl = l & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = (r0 + rows_per_blk < nrows) ? r0 + rows_per_blk : nrows;
+    d4 acc[MTW][NT];
+#pragma unroll
+    for (int i = 0; i < MTW; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = d4zero();
+    int colx[MTW];
+    bool okx[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; i++) {
+        colx[i] = 16 * (wm * MTW + i) + cl;
+        okx[i] = colx[i] < p;
+    }
+    constexpr int U = 2;
+    for (int64_t rb = r0 + (int64_t)wr * 4 * U; rb < r1; rb += (int64_t)WR * 4 * U) {
+        double xa[U][MTW], yb[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t row = rb + 4 * u + g;
+            const bool rv = row < r1;
+#pragma unroll
+            for (int i = 0; i < MTW; i++) xa[u][i] = (rv && okx[i]) ? X[row * ldx + colx[i]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                const int cy = 16 * j + cl;
+                const bool ok = rv && cy < q;
+                yb[u][j] = ok ? Y0[row * ld0 + cy] : 0.0;
+                yb[u][NB + j] = ok ? Y1[row * ld1 + cy] : 0.0;
+                yb[u][2 * NB + j] = ok ? Y2[row * ld2 + cy] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int i = 0; i < MTW; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++) acc[i][j] = mfma(xa[u][i], yb[u][j], acc[i][j]);
+    }
+    if (WR > 1) {
+        if (wr > 0) {
+#pragma unroll
+            for (int i = 0; i < MTW; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++) red[(((wr - 1) * WM + wm) * MTW * NT + i * NT + j) * 64 + l] = acc[i][j];
+        }
+        __syncthreads();
+        if (wr == 0) {
+            for (int r = 1; r < WR; r++)
+#pragma unroll
+                for (int i = 0; i < MTW; i++)
+#pragma unroll
+                    for (int j = 0; j < NT; j++) acc[i][j] += red[(((r - 1) * WM + wm) * MTW * NT + i * NT + j) * 64 + l];
+        }
+    }
+    if (wr == 0) {
+        double* out = part + (int64_t)blockIdx.x * (16 * MT) * (16 * NT);
+#pragma unroll
+        for (int i = 0; i < MTW; i++)
+#pragma unroll
+            for (int j = 0; j < NT; j++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int row = 16 * (wm * MTW + i) + drow(l, v);
+                    out[row * (16 * NT) + 16 * j + cl] = acc[i][j][v];
+                }
+    }
+}
+
 // out[i] = sum over parts of part[p][i] in a fixed order (deterministic).
 // A workgroup owns 64 consecutive elements (one per lane) and its 16
 // wavefronts each sum a contiguous range of the parts, so every load of a
@@ -340,6 +428,31 @@ hipError_t launch_small_ew(int M, int N, double a, const double* X, int64_t ldx,
                            ldx, p, Y, ldy, q, rows_per_blk, part);                          \
         return hipGetLastError();                                                           \
     }
+
+hipError_t launch_xty3_partial(int mt, int nb, int64_t nrows, const double* X, int64_t ldx, int p, const double* Y0,
+                               int64_t ld0, const double* Y1, int64_t ld1, const double* Y2, int64_t ld2, int q,
+                               int nblk, int64_t rows_per_blk, double* part, hipStream_t st) {
+#define XTY3_CASE(MT, NB)                                                                                      \
+    if (mt == MT && nb == NB) {                                                                                \
+        hipLaunchKernelGGL((k_xty3_partial<MT, NB>), dim3(nblk), dim3(256), 0, st, nrows, X, ldx, p, Y0, ld0, Y1, \
+                           ld1, Y2, ld2, q, rows_per_blk, part);                                               \
+        return hipGetLastError();                                                                              \
+    }
+    XTY3_CASE(1, 1)
+    XTY3_CASE(1, 2)
+    XTY3_CASE(1, 4)
+    XTY3_CASE(2, 1)
+    XTY3_CASE(2, 2)
+    XTY3_CASE(2, 4)
+    XTY3_CASE(4, 1)
+    XTY3_CASE(4, 2)
+    XTY3_CASE(4, 4)
+    XTY3_CASE(8, 1)
+    XTY3_CASE(8, 2)
+    XTY3_CASE(8, 4)
+#undef XTY3_CASE
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
                               const double* Y, int64_t ldy, int q, int nblk, int64_t rows_per_blk,

@@ -29,7 +29,7 @@ namespace {
 struct BwdPlan {
     int KP, K0P, QP0;
     XtyPlan xp;
-    double *part, *CA, *CQ, *CG, *CA1, *Z, *N, *Gb, *Yb;
+    double *part, *C3, *CA, *CQ, *CG, *CA1, *Z, *N, *Gb, *Yb;
     double *Qu, *Qub;
     double *MQ, *gRu, *Mk, *CL, *RT, *RiT, *CM;
     double *Pm, *Tm, *Tb, *A1t, *Pb, *TmI, *TbL, *M1, *CL1, *B1m, *Li;
@@ -46,7 +46,7 @@ void make_bwd_plan(int64_t n, int64_t k0, int64_t k, void* ws, BwdPlan& P) {
     const size_t nk = (size_t)std::max(P.K0P, 16) * P.KP;
     const size_t kk = (size_t)P.KP * P.KP;
     const size_t k00 = (size_t)std::max<int64_t>(k0, 1) * std::max<int64_t>(k0, 1);
-    P.part = cv.take((size_t)P.xp.nblk * std::max(nk, kk));
+    P.part = cv.take((size_t)P.xp.nblk * std::max(3 * nk, kk));
     P.MQ = cv.take(kk);
     P.gRu = cv.take(kk);
     P.Mk = cv.take(kk);
@@ -57,9 +57,11 @@ void make_bwd_plan(int64_t n, int64_t k0, int64_t k, void* ws, BwdPlan& P) {
     const size_t pkn = (size_t)std::max(std::max(P.K0P, P.KP), 16) * std::max(P.QP0, P.KP);
     for (auto& p : P.pk) p = cv.take(pkn);
     if (k0 > 0) {
-        P.CA = cv.take(nk);
-        P.CQ = cv.take(nk);
-        P.CG = cv.take(nk);
+        // V^T [A, Q, G_Q] side by side (ld 3 KP)
+        P.C3 = cv.take(3 * nk);
+        P.CA = P.C3;
+        P.CQ = P.C3 + P.KP;
+        P.CG = P.C3 + 2 * P.KP;
         P.CA1 = cv.take(nk);
         P.Z = cv.take(nk);
         P.N = cv.take(nk);
@@ -70,7 +72,7 @@ void make_bwd_plan(int64_t n, int64_t k0, int64_t k, void* ws, BwdPlan& P) {
         P.Qub = cv.take((size_t)(n - k0) * k);
         for (double** p : {&P.Pm, &P.Tm, &P.Tb, &P.Pb, &P.TmI, &P.TbL, &P.M1, &P.CL1, &P.B1m, &P.Li}) *p = cv.take(k00);
     } else {
-        P.CA = P.CQ = P.CG = P.CA1 = P.Z = P.N = P.Gb = P.Yb = P.A1t = P.Qu = P.Qub = nullptr;
+        P.C3 = P.CA = P.CQ = P.CG = P.CA1 = P.Z = P.N = P.Gb = P.Yb = P.A1t = P.Qu = P.Qub = nullptr;
         P.Pm = P.Tm = P.Tb = P.Pb = P.TmI = P.TbL = P.M1 = P.CL1 = P.B1m = P.Li = nullptr;
     }
     P.bytes = cv.bytes();
@@ -193,18 +195,19 @@ int tho_two_stage_backward(int32_t dtype, int64_t n, int64_t k0, int64_t k, cons
         HIPCHK(hipStreamWaitEvent(f.side, f.ev0, 0));
         PROF("qr_top", f.side, launch_qr_top(ik0, V, ldv, P.Pm, P.Tm, f.side));
         HIPCHK(hipEventRecord(f.ev1, f.side));
-        if ((rc = xty(P.xp, n, V, ldv, ik0, A, lda, ik, P.part, P.CA, st, "xty_partial"))) return rc;
-        if ((rc = xty(P.xp, n, V, ldv, ik0, Q, ldq, ik, P.part, P.CQ, st, "xty_partial"))) return rc;
-        if ((rc = xty(P.xp, n, V, ldv, ik0, gQ, ldgq, ik, P.part, P.CG, st, "xty_partial"))) return rc;
+        // the three reductions in one pass over V
+        PROF("xty3_partial", st, launch_xty3_partial(K0P / 16, KP / 16, n, V, ldv, ik0, A, lda, Q, ldq, gQ, ldgq, ik,
+                                                     P.xp.nblk, P.xp.rows_per_blk, P.part, st));
+        PROF("reduce_parts", st, launch_reduce_parts(P.xp.nblk, (int64_t)K0P * 3 * KP, P.part, P.C3, st));
         HIPCHK(hipStreamWaitEvent(st, f.ev1, 0));
         // Z = T^{-T} W^T A,  W^T A = P^T A_top - V^T A
-        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.CA, KP, P.Z, KP, st));
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, P.Pm, k0, 1, A, lda, 0, -1.0, P.CA, 3 * KP, P.Z, KP, st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Z, KP, st));
         // N = -T^{-T} W^T Q
-        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 1, Q, ldq, 0, 1.0, P.CQ, KP, P.N, KP, st));
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 1, Q, ldq, 0, 1.0, P.CQ, 3 * KP, P.N, KP, st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.N, KP, st));
         // (Q) adjoint: N_bar = -W^T Q_bar, G_bar = T^{-T} N_bar
-        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 1, gQ, ldgq, 0, 1.0, P.CG, KP, P.Gb, KP,
+        PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, -1.0, P.Pm, k0, 1, gQ, ldgq, 0, 1.0, P.CG, 3 * KP, P.Gb, KP,
                                                  st));
         PROF("trsm", st, launch_trsm_lower(ik0, ik, P.Tm, k0, 1, P.Gb, KP, st));
         // Q_ = Q_low - V_low N ;  Q__bar = Q_bar_low - V_low G_bar  (X_bar = Q_bar + W G_bar)

@@ -52,6 +52,11 @@ struct TsqrLevel {
     double* Cfin;
 };
 
+// part[blk] = X^T [Y0 Y1 Y2] over the block's rows for three matrices of q
+// columns each: (16 mt) x (48 nb) per block, the Y_i blocks side by side.
+hipError_t launch_xty3_partial(int mt, int nb, int64_t nrows, const double* X, int64_t ldx, int p, const double* Y0,
+                               int64_t ld0, const double* Y1, int64_t ld1, const double* Y2, int64_t ld2, int q,
+                               int nblk, int64_t rows_per_blk, double* part, hipStream_t st);
 hipError_t launch_xty_partial(int mt, int nt, int64_t nrows, const double* X, int64_t ldx, int p,
                               const double* Y, int64_t ldy, int q, int nblk, int64_t rows_per_blk,
                               double* part, hipStream_t st);
