@@ -157,7 +157,7 @@ __device__ __forceinline__ void run_instance(const BatchedInst& I, const TsqrLev
         __syncthreads();
         for (int e = tid; e < K0P * KP; e += BW) {
             const int ln = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
-            I.Nperm[e] = Ns[((ln >> 4) * (K0P / 4) + s) * LDC + 16 * ct + (ln & 15)];
+            I.Nperm[e] = Ns[rows_kidx(s, ln >> 4) * LDC + 16 * ct + (ln & 15)];
         }
         // Q_top = -(P - V_top) N
         for (int e = tid; e < k0 * k; e += BW) {

@@ -393,6 +393,16 @@ __global__ void k_permute_b(int K0P, int KP, const double* __restrict__ src, dou
     }
 }
 
+// dst[(s*CT + ct)*64 + l] = src[rows_kidx(s, l/16)*KP + 16*ct + l%16]: the
+// B operand of the formation's row products (K split as in rows_kidx).
+__global__ void k_permute_b_rows(int K0P, int KP, const double* __restrict__ src, double* __restrict__ dst) {
+    const int n = K0P * KP, CT = KP / 16;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int l = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
+        dst[e] = src[rows_kidx(s, l >> 4) * KP + 16 * ct + (l & 15)];
+    }
+}
+
 // D = a op(X) + b op(Y) + c I (M x N), masked: mode 1 keeps j <= i, mode 2
 // keeps j >= i, mode 3 mirrors the lower part to the upper (copyltu).
 __global__ void k_small_ew(int M, int N, double a, const double* __restrict__ X, int64_t ldx, int tx, double b,
@@ -523,6 +533,11 @@ hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, doubl
 
 hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st) {
     hipLaunchKernelGGL(k_permute_b, dim3((K0P * KP + 255) / 256), dim3(256), 0, st, K0P, KP, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_b_rows(int K0P, int KP, const double* src, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute_b_rows, dim3((K0P * KP + 255) / 256), dim3(256), 0, st, K0P, KP, src, dst);
     return hipGetLastError();
 }
 

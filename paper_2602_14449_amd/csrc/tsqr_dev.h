@@ -799,7 +799,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
             }
         }
         // + V N: K-steps outer so that each B-operand load of N serves every
-        // row block (N is read in operand order, see k_permute_b)
+        // row block (N is read in operand order, see k_permute_b_rows)
         if (PANEL == PANEL_F64 && HASV && k0 > 0) {
             constexpr int SC = 4;  // K-steps per batch of loads
 #pragma unroll 2
@@ -808,9 +808,11 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) {
                     const int yr = RPW * w + 16 * rb + cl;
-                    const double* vp = Vt + yr * ldv + g * KS0 + s0;
 #pragma unroll
-                    for (int s = 0; s < SC; s++) a[rb][s] = (yr < trows && g * KS0 + s0 + s < k0) ? vp[s] : 0.0;
+                    for (int s = 0; s < SC; s++) {
+                        const int kk = rows_kidx(s0 + s, g);
+                        a[rb][s] = (yr < trows && kk < k0) ? Vt[yr * ldv + kk] : 0.0;
+                    }
                 }
 #pragma unroll
                 for (int s = 0; s < SC; s++)
@@ -991,10 +993,11 @@ __device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
 }
 
 // acc[rb][ct] += X[rows, :] B over the rows RPW w + 16 rb + (0..15) of a
-// tile: X row-major (ld ldx), contraction index g * KS + s (a lane reads KS
-// consecutive entries of its row; columns >= kmax read as zero), B a
-// (4 KS) x (16 CT) matrix in B-operand order.  K-steps are taken eight at a
-// time, each B load serving every row block.
+// tile: X row-major (ld ldx), contraction index rows_kidx(s, g) (each batch
+// of K-steps consumes whole 128-byte lines of the rows it touches; columns
+// >= kmax read as zero), B a (4 KS) x (16 CT) matrix in B-operand order
+// (k_permute_b_rows).  K-steps are taken eight at a time, each B load
+// serving every row block.
 template <int RB, int CT, int KS>
 __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
                                           int trows, int kmax, const double* __restrict__ B, int l) {
@@ -1006,9 +1009,11 @@ __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __res
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
             const int xr = row0 + 16 * rb + cl;
-            const double* xp = X + xr * ldx + g * KS + s0;
 #pragma unroll
-            for (int s = 0; s < SC; s++) a[rb][s] = (xr < trows && g * KS + s0 + s < kmax) ? xp[s] : 0.0;
+            for (int s = 0; s < SC; s++) {
+                const int kk = rows_kidx(s0 + s, g);
+                a[rb][s] = (xr < trows && kk < kmax) ? X[xr * ldx + kk] : 0.0;
+            }
         }
 #pragma unroll
         for (int s = 0; s < SC; s++)
@@ -1024,8 +1029,8 @@ __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __res
 }
 
 // rows_prod for a full tile (every row present, kmax = 4 KS) with X 16-byte
-// aligned and ldx even: no masks, so each lane's KS-long row piece is read
-// with 16-byte loads.
+// aligned and ldx even: no masks, so each lane reads its two adjacent
+// columns of a K-step pair with one 16-byte load.
 template <int RB, int CT, int KS>
 __device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
                                                const double* __restrict__ B, int l) {
@@ -1036,10 +1041,10 @@ __device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* 
         double a[RB][SC], b[SC][CT];
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
-            const double2* xp = (const double2*)(X + (row0 + 16 * rb + cl) * ldx + g * KS + s0);
+            const double* xr = X + (row0 + 16 * rb + cl) * ldx;
 #pragma unroll
             for (int s = 0; s < SC / 2; s++) {
-                const double2 z = xp[s];
+                const double2 z = *(const double2*)(xr + rows_kidx(s0 + 2 * s, g));
                 a[rb][2 * s] = z.x;
                 a[rb][2 * s + 1] = z.y;
             }
