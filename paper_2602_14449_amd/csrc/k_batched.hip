@@ -106,7 +106,7 @@ __device__ __forceinline__ void run_instance(const BatchedInst& I, const TsqrLev
         __syncthreads();
         for (int e = tid; e < K0P * KP; e += BW) {
             const int ln = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
-            I.Zperm[e] = Zs[((ln >> 4) * (K0P / 4) + s) * LDC + 16 * ct + (ln & 15)];
+            I.Zperm[e] = Zs[rows_kidx(s, ln >> 4) * LDC + 16 * ct + (ln & 15)];
         }
         // A1_top = A_top - (P - V_top) Z
         for (int e = tid; e < k0 * k; e += BW) {

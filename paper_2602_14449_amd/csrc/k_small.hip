@@ -382,20 +382,10 @@ __global__ __launch_bounds__(256) void k_chunk_prod(int K0P, int KP, int k, cons
     }
 }
 
-// dst[(s*CT + ct)*64 + l] = src[((l/16)*(K0P/4) + s)*KP + 16*ct + l%16]: a
+// dst[(s*CT + ct)*64 + l] = src[rows_kidx(s, l/16)*KP + 16*ct + l%16]: a
 // K0P x KP matrix in the order in which 64 lanes read it as the B operand
-// of FP64 MFMA K-steps whose K index is split as (l/16)*(K0P/4) + s.
+// of FP64 MFMA K-steps whose K index is split as rows_kidx(s, l/16).
 __global__ void k_permute_b(int K0P, int KP, const double* __restrict__ src, double* __restrict__ dst) {
-    const int n = K0P * KP, KS = K0P / 4, CT = KP / 16;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int l = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
-        dst[e] = src[((l >> 4) * KS + s) * KP + 16 * ct + (l & 15)];
-    }
-}
-
-// dst[(s*CT + ct)*64 + l] = src[rows_kidx(s, l/16)*KP + 16*ct + l%16]: the
-// B operand of the formation's row products (K split as in rows_kidx).
-__global__ void k_permute_b_rows(int K0P, int KP, const double* __restrict__ src, double* __restrict__ dst) {
     const int n = K0P * KP, CT = KP / 16;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int l = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
@@ -536,10 +526,6 @@ hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hip
     return hipGetLastError();
 }
 
-hipError_t launch_permute_b_rows(int K0P, int KP, const double* src, double* dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_permute_b_rows, dim3((K0P * KP + 255) / 256), dim3(256), 0, st, K0P, KP, src, dst);
-    return hipGetLastError();
-}
 
 hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
                              int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st) {

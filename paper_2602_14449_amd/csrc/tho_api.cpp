@@ -247,7 +247,7 @@ int run_two_stage(int64_t n, int64_t k0, int64_t k, const double* V, int64_t ldv
         PROF("small_gemm", st, launch_small_gemm(K0P, KP, 0, 0.0, P.Mbuf, KP, 0, P.Mbuf, KP, 0, -1.0, P.Mbuf, KP,
                                  P.Nglob, KP, st));
         if ((rc = solve_t(pchoice, ik0, ik, P.Tm, P.F2, P.Nglob, KP, st))) return rc;
-        PROF("permute", st, launch_permute_b_rows(K0P, KP, P.Nglob, P.Nperm, st));
+        PROF("permute", st, launch_permute_b(K0P, KP, P.Nglob, P.Nperm, st));
         if (panel) PROF("pack_lowp", st, launch_pack_b_lowp(panel, K0P, KP, P.Nglob, P.Nlp, st));
         // Q_top = -(P - V_top) N
         PROF("small_gemm", st, launch_small_gemm(ik0, ik, ik0, 1.0, V, ldv, 0, P.Nglob, KP, 0, 0.0, nullptr, 0, Q, ldq,

@@ -164,11 +164,12 @@ __device__ __forceinline__ double sum_wave(double x) {
 
 __device__ __forceinline__ double ldg(const double* p) { return __builtin_nontemporal_load(p); }
 
-// K index of K-step s for lane group g in the row products of the formation
-// (X N with X streamed from HBM): a pair of K-steps takes two adjacent
-// columns and the four lane groups sit side by side, so that one 16-byte
-// load per lane covers 64 contiguous bytes of each of 16 rows and two
-// consecutive pairs a whole 128-byte line.  K must be a multiple of 8.
+// K index of K-step s for lane group g in the MFMA row products X B whose X
+// streams from HBM (the update A + V Z, the formation's V N): a pair of
+// K-steps takes two adjacent columns and the four lane groups sit side by
+// side, so that one 16-byte load per lane covers 64 contiguous bytes of each
+// of 16 rows and two consecutive pairs a whole 128-byte line.  K must be a
+// multiple of 8.
 __host__ __device__ constexpr int rows_kidx(int s, int g) { return 8 * (s >> 1) + 2 * g + (s & 1); }
 
 }  // namespace tho

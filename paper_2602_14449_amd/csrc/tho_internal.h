@@ -92,7 +92,6 @@ hipError_t launch_vorth_check(int k0, int cplx, const double* G0, int ld0, const
 hipError_t launch_finish_r(int k, int KP, const double* Rin, int64_t ldri, double* Rout, int64_t ldr,
                            double* G0, hipStream_t st);
 hipError_t launch_permute_b(int K0P, int KP, const double* src, double* dst, hipStream_t st);
-hipError_t launch_permute_b_rows(int K0P, int KP, const double* src, double* dst, hipStream_t st);
 hipError_t launch_chunk_prod(int nchunk, int K0P, int KP, int k, const double* Nc, const double* Gbase,
                              int64_t ldg, int64_t grow_stride, double* prod, hipStream_t st);
 

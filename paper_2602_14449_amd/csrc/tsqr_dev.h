@@ -460,10 +460,11 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) {
                     const int vr = RPW * w + 16 * rb + cl;  // A-operand row of this lane
-                    const double* vp = Vt + vr * ldv + g * KS0 + s0;
 #pragma unroll
-                    for (int s = 0; s < SC; s++)
-                        a[rb][s] = (vr < trows && g * KS0 + s0 + s < k0) ? vp[s] : 0.0;
+                    for (int s = 0; s < SC; s++) {
+                        const int kk = rows_kidx(s0 + s, g);  // a batch reads whole lines of V
+                        a[rb][s] = (vr < trows && kk < k0) ? Vt[vr * ldv + kk] : 0.0;
+                    }
                 }
 #pragma unroll
                 for (int s = 0; s < SC; s++)
@@ -799,7 +800,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
             }
         }
         // + V N: K-steps outer so that each B-operand load of N serves every
-        // row block (N is read in operand order, see k_permute_b_rows)
+        // row block (N is read in operand order, see k_permute_b)
         if (PANEL == PANEL_F64 && HASV && k0 > 0) {
             constexpr int SC = 4;  // K-steps per batch of loads
 #pragma unroll 2
@@ -996,7 +997,7 @@ __device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
 // tile: X row-major (ld ldx), contraction index rows_kidx(s, g) (each batch
 // of K-steps consumes whole 128-byte lines of the rows it touches; columns
 // >= kmax read as zero), B a (4 KS) x (16 CT) matrix in B-operand order
-// (k_permute_b_rows).  K-steps are taken eight at a time, each B load
+// (k_permute_b).  K-steps are taken eight at a time, each B load
 // serving every row block.
 template <int RB, int CT, int KS>
 __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
