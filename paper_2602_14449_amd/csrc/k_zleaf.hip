@@ -360,7 +360,7 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zleaf_rt(ZRLevel L) {
                     const int vr = RPW * w + 16 * rb + cl;
 #pragma unroll
                     for (int s = 0; s < SC; s++) {
-                        const int kk = g * KS0 + s0 + s;
+                        const int kk = 4 * (s0 + s) + g;  // a K-step pair reads whole lines of V
                         double2 z = make_double2(0.0, 0.0);
                         if (vr < trows && kk < k0) z = ld2(Vt + 2 * (vr * ldv + kk));
                         ar_[rb][s] = z.x;
@@ -663,15 +663,16 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zleaf_rt(ZRLevel L) {
 }
 
 // Z (k0 x k complex, ld ldz) into the B-operand order of the fused update:
-// entry ((s * CT + ct) * 64 + l) holds Z[(l / 16) * KS + s][16 ct + l % 16]
-// (KS = K0P / 4), zero outside k0 x k.
+// entry ((s * CT + ct) * 64 + l) holds Z[4 s + l / 16][16 ct + l % 16] (the
+// four lane groups take adjacent K indices, so that two K-steps read whole
+// 128-byte lines of the streamed rows), zero outside k0 x k.
 __global__ void k_zpermute_b(int k0p, int kp, int k0, int k, const dcplx* __restrict__ Z, int64_t ldz, dcplx* out) {
     const int ks = k0p / 4, ct_n = kp / 16;
     const int total = ks * ct_n * 64;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
         const int l = e & 63, sct = e >> 6;
         const int s = sct / ct_n, ct = sct % ct_n;
-        const int r = (l >> 4) * ks + s, cc = 16 * ct + (l & 15);
+        const int r = 4 * s + (l >> 4), cc = 16 * ct + (l & 15);
         out[e] = (r < k0 && cc < k) ? Z[(int64_t)r * ldz + cc] : dcplx{0.0, 0.0};
     }
 }
@@ -855,7 +856,7 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zrows(ZLevel L, const dcplx* Cf
                 const int xr = RPW * w + 16 * rb + cl;
 #pragma unroll
                 for (int s = 0; s < SC; s++) {
-                    const int kk = g * KS0 + s0 + s;
+                    const int kk = 4 * (s0 + s) + g;
                     double2 z = make_double2(0.0, 0.0);
                     if (xr < trows && kk < k0) z = ld2(Vt + 2 * (xr * ldv + kk));
                     vr[rb][s] = z.x;
