@@ -848,7 +848,7 @@ __device__ __forceinline__ void form_chunk(const TsqrLevel& L, const int c) {
 // one above it (top-down: K_t = T_t C, C <- C - K_t for a structured tile;
 // K_0 = T_0 L_0^T C for the plain tile 0, whose top k rows also receive C).
 // kchain_chunk walks that recurrence for one chunk and overwrites every T_t
-// in place with -K_t (in B-operand order, see k_permute_b) and stores the
+// in place with -K_t (in B-operand order, K split by rows_kidx) and stores the
 // final C; rows_tile then forms the Q rows of any tile on its own,
 //   Q_t = [C; 0] (tile 0 only) - Y_t K_t + V_t N,
 // with no barrier and no shared memory, so that the streaming MFMA work runs
@@ -980,7 +980,8 @@ __device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
                     const int r = 16 * mi + drow(l, v), cc = 16 * nj + cl;
-                    Kg[((r % KSK) * CT + nj) * 64 + 16 * (r / KSK) + cl] = -kk[i][v];
+                    // row r of K is K-step s, lane group g with r = rows_kidx(s, g)
+                    Kg[((2 * (r >> 3) + (r & 1)) * CT + nj) * 64 + 16 * ((r >> 1) & 3) + cl] = -kk[i][v];
                     if (!plain) Cm[r * LDT + cc] -= kk[i][v];
                 }
             }
@@ -1035,11 +1036,12 @@ __device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __res
 template <int RB, int CT, int KS>
 __device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
                                                const double* __restrict__ B, int l) {
-    constexpr int SC = (KS < 8) ? KS : 8;
+    constexpr int SC = 4;          // K-steps per batch: one 128-byte line of each row
+    constexpr int NBT = KS / SC;   // batches
+    static_assert(NBT * SC == KS, "KS must be a multiple of 4");
     const int g = l >> 4, cl = l & 15;
-#pragma unroll 2
-    for (int s0 = 0; s0 < KS; s0 += SC) {
-        double a[RB][SC], b[SC][CT];
+    // the loads of batch ib + 1 are issued before the MFMAs of batch ib
+    auto load = [&](int s0, double(&a)[RB][SC], double(&b)[SC][CT]) {
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
             const double* xr = X + (row0 + 16 * rb + cl) * ldx;
@@ -1054,12 +1056,19 @@ __device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* 
         for (int s = 0; s < SC; s++)
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
+    };
+    double a[2][RB][SC], b[2][SC][CT];
+    load(0, a[0], b[0]);
+#pragma unroll
+    for (int ib = 0; ib < NBT; ib++) {
+        const int cur = ib & 1;
+        if (ib + 1 < NBT) load((ib + 1) * SC, a[cur ^ 1], b[cur ^ 1]);
 #pragma unroll
         for (int s = 0; s < SC; s++)
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[cur][rb][s], b[cur][s][ct], acc[rb][ct]);
     }
 }
 
@@ -1106,43 +1115,15 @@ __device__ __forceinline__ void rows_tile(const TsqrLevel& L, const int c, const
     // a full tile with 16-byte aligned rows takes the unmasked paths
     const bool full = trows == TB && k == KP && (!HASV || k0 == K0P) && ((ldy | (HASV ? ldv : 0)) & 1) == 0 &&
                       ((((uintptr_t)Yt) | ((uintptr_t)Vt)) & 15) == 0;
-    // - Y_t K_t: all KSK K-steps at once (the loads of Y and of K_t are
-    // issued together, deepest memory-level parallelism)
-    if (full) {
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const double2* yp = (const double2*)(Yt + (RPW * w + 16 * rb + cl) * ldy + g * KSK);
-            double a[KSK];
-#pragma unroll
-            for (int s = 0; s < KSK / 2; s++) {
-                const double2 z = yp[s];
-                a[2 * s] = z.x;
-                a[2 * s + 1] = z.y;
-            }
-#pragma unroll
-            for (int s = 0; s < KSK; s++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[s], Kg[(s * CT + ct) * 64 + l], acc[rb][ct]);
-        }
-    } else {
-        const int g = l >> 4, cl = l & 15;
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const int yr = RPW * w + 16 * rb + cl;
-            const double* yp = Yt + yr * ldy + g * KSK;
-            double a[KSK];
-#pragma unroll
-            for (int s = 0; s < KSK; s++) a[s] = (yr < trows && g * KSK + s < k) ? yp[s] : 0.0;
-#pragma unroll
-            for (int s = 0; s < KSK; s++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[s], Kg[(s * CT + ct) * 64 + l], acc[rb][ct]);
-        }
-    }
+    // - Y_t K_t (-K_t in B-operand order from the K chain)
+    if (full) rows_prod_full<RB, CT, KSK>(acc, Yt, ldy, RPW * w, Kg, l);
+    else rows_prod<RB, CT, KSK>(acc, Yt, ldy, RPW * w, trows, k, Kg, l);
     // + V_t N (N in B-operand order, see k_permute_b)
-    if (PANEL == PANEL_F64 && HASV && k0 > 0) {
-        if (full) rows_prod_full<RB, CT, KS0>(acc, Vt, ldv, RPW * w, L.Nglob, l);
-        else rows_prod<RB, CT, KS0>(acc, Vt, ldv, RPW * w, trows, k0, L.Nglob, l);
+    if constexpr (PANEL == PANEL_F64 && HASV) {
+        if (k0 > 0) {
+            if (full) rows_prod_full<RB, CT, KS0>(acc, Vt, ldv, RPW * w, L.Nglob, l);
+            else rows_prod<RB, CT, KS0>(acc, Vt, ldv, RPW * w, trows, k0, L.Nglob, l);
+        }
     }
     if (PANEL != PANEL_F64 && HASV && k0 > 0)
         vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(acc, Vt, ldv, RPW * w, trows, k0, L.Nlp, l);
