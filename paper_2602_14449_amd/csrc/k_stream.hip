@@ -11,9 +11,9 @@
 // Each wavefront owns RB 16-row blocks (RB = 4 up to 64 output columns,
 // 2 for 128) and keeps the output block in MFMA accumulator layout, so X is
 // read and Out written by the same lane (Out may alias X).  The contraction
-// index of term t is split as (lane / 16) * (kpad_t / 4) + s: a lane reads
-// kpad_t / 4 consecutive entries of one row of Y_t, so a row's cache lines
-// are consumed by one 16-lane group over the K loop.
+// index of term t is split as rows_kidx(s, lane / 16): each batch of four
+// K-steps reads one whole 128-byte line of every row it touches, the four
+// lane groups side by side.
 #include "tho_device.h"
 #include "tho_internal.h"
 
@@ -22,7 +22,7 @@ namespace tho {
 namespace {
 
 template <int CT, int RB>
-__global__ __launch_bounds__(256) void k_rows_gemm(RowsGemm g) {
+__global__ __launch_bounds__(256, 2) void k_rows_gemm(RowsGemm g) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, gq = l >> 4, cl = l & 15;
     const int64_t wr0 = (int64_t)blockIdx.x * (4 * 16 * RB) + (int64_t)w * 16 * RB;
     const int64_t nrows = g.nrows;
@@ -48,10 +48,11 @@ __global__ __launch_bounds__(256) void k_rows_gemm(RowsGemm g) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++) {
                 const int64_t row = wr0 + 16 * rb + cl;
-                const int c0 = gq * KS + s0;
 #pragma unroll
-                for (int s = 0; s < 4; s++)
-                    a[rb][s] = (row < nrows && c0 + s < p) ? Y[row * ldy + c0 + s] : 0.0;
+                for (int s = 0; s < 4; s++) {
+                    const int c = rows_kidx(s0 + s, gq);
+                    a[rb][s] = (row < nrows && c < p) ? Y[row * ldy + c] : 0.0;
+                }
             }
 #pragma unroll
             for (int s = 0; s < 4; s++)
@@ -80,13 +81,13 @@ __global__ __launch_bounds__(256) void k_rows_gemm(RowsGemm g) {
 // dst (kpad x qp, B-operand order) = scale * op(src) zero-padded, where
 // op(src)(i, j) = src[i*lds + j] (trans == 0) or src[j*lds + i] (trans == 1)
 // for i < p, j < q.  Element e of dst: lane l = e % 64, K-step s and column
-// tile ct from e / 64, holding B[(l/16)*(kpad/4) + s][16 ct + l%16].
+// tile ct from e / 64, holding B[rows_kidx(s, l/16)][16 ct + l%16].
 __global__ void k_pack_b(int p, int q, const double* __restrict__ src, int64_t lds, int trans, double scale,
                          int kpad, int qp, double* __restrict__ dst) {
-    const int n = kpad * qp, KS = kpad / 4, CT = qp / 16;
+    const int n = kpad * qp, CT = qp / 16;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int l = e & 63, sc = e >> 6, s = sc / CT, ct = sc % CT;
-        const int i = (l >> 4) * KS + s, j = 16 * ct + (l & 15);
+        const int i = rows_kidx(s, l >> 4), j = 16 * ct + (l & 15);
         double v = 0.0;
         if (i < p && j < q) v = scale * (trans ? src[(int64_t)j * lds + i] : src[(int64_t)i * lds + j]);
         dst[e] = v;
