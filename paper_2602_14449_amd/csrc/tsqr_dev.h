@@ -386,6 +386,84 @@ __device__ __forceinline__ void tile_t_factor(double* TG, const double* taus, in
 
 }  // namespace
 
+// acc[rb][ct] += X[rows, :] B over the rows RPW w + 16 rb + (0..15) of a
+// tile: X row-major (ld ldx), contraction index rows_kidx(s, g) (each batch
+// of K-steps consumes whole 128-byte lines of the rows it touches; columns
+// >= kmax read as zero), B a (4 KS) x (16 CT) matrix in B-operand order
+// (k_permute_b).  K-steps are taken eight at a time, each B load
+// serving every row block.
+template <int RB, int CT, int KS>
+__device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
+                                          int trows, int kmax, const double* __restrict__ B, int l) {
+    constexpr int SC = (KS < 8) ? KS : 8;
+    const int g = l >> 4, cl = l & 15;
+#pragma unroll 2
+    for (int s0 = 0; s0 < KS; s0 += SC) {
+        double a[RB][SC], b[SC][CT];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const int xr = row0 + 16 * rb + cl;
+#pragma unroll
+            for (int s = 0; s < SC; s++) {
+                const int kk = rows_kidx(s0 + s, g);
+                a[rb][s] = (xr < trows && kk < kmax) ? X[xr * ldx + kk] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
+    }
+}
+
+// rows_prod for a full tile (every row present, kmax = 4 KS) with X 16-byte
+// aligned and ldx even: no masks, so each lane reads its two adjacent
+// columns of a K-step pair with one 16-byte load.
+template <int RB, int CT, int KS>
+__device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
+                                               const double* __restrict__ B, int l) {
+    constexpr int SC = 4;          // K-steps per batch: one 128-byte line of each row
+    constexpr int NBT = KS / SC;   // batches
+    static_assert(NBT * SC == KS, "KS must be a multiple of 4");
+    const int g = l >> 4, cl = l & 15;
+    // the loads of batch ib + 1 are issued before the MFMAs of batch ib
+    auto load = [&](int s0, double(&a)[RB][SC], double(&b)[SC][CT]) {
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const double* xr = X + (row0 + 16 * rb + cl) * ldx;
+#pragma unroll
+            for (int s = 0; s < SC / 2; s++) {
+                const double2 z = *(const double2*)(xr + rows_kidx(s0 + 2 * s, g));
+                a[rb][2 * s] = z.x;
+                a[rb][2 * s + 1] = z.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
+    };
+    double a[2][RB][SC], b[2][SC][CT];
+    load(0, a[0], b[0]);
+#pragma unroll
+    for (int ib = 0; ib < NBT; ib++) {
+        const int cur = ib & 1;
+        if (ib + 1 < NBT) load((ib + 1) * SC, a[cur ^ 1], b[cur ^ 1]);
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[cur][rb][s], b[cur][s][ct], acc[rb][ct]);
+    }
+}
+
 template <int KP, int K0P, int PANEL, int RBO, int NWT = NW>
 __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
     constexpr int RB = Geo<KP, RBO, NWT>::RB, RPW = Geo<KP, RBO, NWT>::RPW, TB = Geo<KP, RBO, NWT>::TB;
@@ -452,10 +530,15 @@ __device__ __forceinline__ void leaf_chunk(const TsqrLevel& L, const int c) {
         if (PANEL != PANEL_F64 && HASV && k0 > 0) {
             vprod_lowp<PANEL, RB, CT, (K0P > 0 ? K0P : 16)>(x, Vt, ldv, RPW * w, trows, k0, L.Zlp, opaque_lane());
         } else if (HASV && k0 > 0) {
+            // a full tile with 16-byte aligned rows takes the unmasked, pipelined product
+            const bool fullv = trows == TB && k0 == K0P && (ldv & 1) == 0 && (((uintptr_t)Vt) & 15) == 0;
+            if constexpr (HASV) {
+                if (fullv) rows_prod_full<RB, CT, KS0>(x, Vt, ldv, RPW * w, L.Z, opaque_lane());
+            }
             const int l = opaque_lane(), g = l >> 4, cl = l & 15;
             constexpr int SC = 4;  // K-steps per chunk
 #pragma unroll 2
-            for (int s0 = 0; s0 < KS0; s0 += SC) {
+            for (int s0 = 0; s0 < (fullv ? 0 : KS0); s0 += SC) {
                 double a[RB][SC], b[SC][CT];
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) {
@@ -992,84 +1075,6 @@ __device__ __forceinline__ void kchain_chunk(const TsqrLevel& L, const int c) {
     // C as the plain tile 0 sees it (zero outside the k x k block)
     double* Cf = L.Cfin + (int64_t)c * KP * KP;
     for (int e = tid; e < KP * KP; e += blockDim.x) Cf[e] = Cm[(e / KP) * LDT + e % KP];
-}
-
-// acc[rb][ct] += X[rows, :] B over the rows RPW w + 16 rb + (0..15) of a
-// tile: X row-major (ld ldx), contraction index rows_kidx(s, g) (each batch
-// of K-steps consumes whole 128-byte lines of the rows it touches; columns
-// >= kmax read as zero), B a (4 KS) x (16 CT) matrix in B-operand order
-// (k_permute_b).  K-steps are taken eight at a time, each B load
-// serving every row block.
-template <int RB, int CT, int KS>
-__device__ __forceinline__ void rows_prod(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
-                                          int trows, int kmax, const double* __restrict__ B, int l) {
-    constexpr int SC = (KS < 8) ? KS : 8;
-    const int g = l >> 4, cl = l & 15;
-#pragma unroll 2
-    for (int s0 = 0; s0 < KS; s0 += SC) {
-        double a[RB][SC], b[SC][CT];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const int xr = row0 + 16 * rb + cl;
-#pragma unroll
-            for (int s = 0; s < SC; s++) {
-                const int kk = rows_kidx(s0 + s, g);
-                a[rb][s] = (xr < trows && kk < kmax) ? X[xr * ldx + kk] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < SC; s++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
-#pragma unroll
-        for (int s = 0; s < SC; s++)
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[rb][s], b[s][ct], acc[rb][ct]);
-    }
-}
-
-// rows_prod for a full tile (every row present, kmax = 4 KS) with X 16-byte
-// aligned and ldx even: no masks, so each lane reads its two adjacent
-// columns of a K-step pair with one 16-byte load.
-template <int RB, int CT, int KS>
-__device__ __forceinline__ void rows_prod_full(d4 (&acc)[RB][CT], const double* __restrict__ X, int ldx, int row0,
-                                               const double* __restrict__ B, int l) {
-    constexpr int SC = 4;          // K-steps per batch: one 128-byte line of each row
-    constexpr int NBT = KS / SC;   // batches
-    static_assert(NBT * SC == KS, "KS must be a multiple of 4");
-    const int g = l >> 4, cl = l & 15;
-    // the loads of batch ib + 1 are issued before the MFMAs of batch ib
-    auto load = [&](int s0, double(&a)[RB][SC], double(&b)[SC][CT]) {
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const double* xr = X + (row0 + 16 * rb + cl) * ldx;
-#pragma unroll
-            for (int s = 0; s < SC / 2; s++) {
-                const double2 z = *(const double2*)(xr + rows_kidx(s0 + 2 * s, g));
-                a[rb][2 * s] = z.x;
-                a[rb][2 * s + 1] = z.y;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < SC; s++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) b[s][ct] = B[((s0 + s) * CT + ct) * 64 + l];
-    };
-    double a[2][RB][SC], b[2][SC][CT];
-    load(0, a[0], b[0]);
-#pragma unroll
-    for (int ib = 0; ib < NBT; ib++) {
-        const int cur = ib & 1;
-        if (ib + 1 < NBT) load((ib + 1) * SC, a[cur ^ 1], b[cur ^ 1]);
-#pragma unroll
-        for (int s = 0; s < SC; s++)
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int ct = 0; ct < CT; ct++) acc[rb][ct] = mfma(a[cur][rb][s], b[cur][s][ct], acc[rb][ct]);
-    }
 }
 
 template <int KP, int K0P, int PANEL>
