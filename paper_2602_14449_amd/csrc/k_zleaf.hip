@@ -287,6 +287,52 @@ __device__ __forceinline__ double zhh_tile(d4 (&xr)[ZGeo<KP>::RB][KP / 16], d4 (
     return cy.beta_prev;
 }
 
+// acr + i aci += X[rows, :] B over the rows row0 + 16 rb + (0..15) of a full
+// tile (every row present, all 4 KS columns valid): X complex row-major (ld
+// ldx, in doubles of pairs), K index 4 s + lane / 16 (two K-steps read a
+// whole 128-byte line of each row), B complex in B-operand order
+// (k_zpermute_b), four real MFMA products per complex one.  Batches of two
+// K-steps; the loads of the next batch are issued before the MFMAs of the
+// current one.
+template <int RB, int CT, int KS>
+__device__ __forceinline__ void zprod_full(d4 (&acr)[RB][CT], d4 (&aci)[RB][CT], const double* __restrict__ X,
+                                           int ldx, int row0, const double* __restrict__ B, int l) {
+    constexpr int SC = 2, NBT = KS / SC;
+    static_assert(NBT * SC == KS, "KS must be even");
+    const int g = l >> 4, cl = l & 15;
+    auto load = [&](int s0, double2(&a)[RB][SC], double2(&b)[SC][CT]) {
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const double* xr = X + 2 * (row0 + 16 * rb + cl) * ldx;
+#pragma unroll
+            for (int s = 0; s < SC; s++) a[rb][s] = ld2(xr + 2 * (4 * (s0 + s) + g));
+        }
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) b[s][ct] = ld2(B + 2 * (((s0 + s) * CT + ct) * 64 + l));
+    };
+    double2 a[2][RB][SC], b[2][SC][CT];
+    load(0, a[0], b[0]);
+#pragma unroll
+    for (int ib = 0; ib < NBT; ib++) {
+        const int cur = ib & 1;
+        if (ib + 1 < NBT) load((ib + 1) * SC, a[cur ^ 1], b[cur ^ 1]);
+#pragma unroll
+        for (int s = 0; s < SC; s++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ct = 0; ct < CT; ct++) {
+                    const double2 x = a[cur][rb][s], y = b[cur][s][ct];
+                    acr[rb][ct] = mfma(x.x, y.x, acr[rb][ct]);
+                    acr[rb][ct] = mfma(-x.y, y.y, acr[rb][ct]);
+                    aci[rb][ct] = mfma(x.x, y.y, aci[rb][ct]);
+                    aci[rb][ct] = mfma(x.y, y.x, aci[rb][ct]);
+                }
+    }
+}
+
 template <int KP, int K0P>
 __global__ __launch_bounds__(ZNW * 64, 2) void k_zleaf_rt(ZRLevel L) {
     constexpr int RB = ZGeo<KP>::RB, RPW = ZGeo<KP>::RPW, TB = ZGeo<KP>::TB, CT = KP / 16, LDT = KP + 1;
@@ -350,10 +396,15 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zleaf_rt(ZRLevel L) {
         // A <- A + V Z (four real MFMA products per complex one; Z in
         // B-operand order, k_zpermute_b)
         if (HASV && k0 > 0) {
+            // a full tile takes the unmasked, pipelined product
+            const bool fullv = trows == TB && k0 == K0P;
+            if constexpr (HASV) {
+                if (fullv) zprod_full<RB, CT, KS0>(xr, xi, Vt, ldv, RPW * w, (const double*)L.Zp, zlane());
+            }
             const int l = zlane(), g = l >> 4, cl = l & 15;
             constexpr int SC = 2;
 #pragma unroll 2
-            for (int s0 = 0; s0 < KS0; s0 += SC) {
+            for (int s0 = 0; s0 < (fullv ? 0 : KS0); s0 += SC) {
                 double ar_[RB][SC], ai_[RB][SC], br_[SC][CT], bi_[SC][CT];
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) {
@@ -847,9 +898,13 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zrows(ZLevel L, const dcplx* Cf
     // + V_t N (N in B-operand order)
     if (K0P > 0 && k0 > 0) {
         const double* Vt = (const double*)(V + r0 * ldv);
+        const bool fullv = trows == TB && k0 == K0P;
+        if constexpr (K0P > 0) {
+            if (fullv) zprod_full<RB, CT, KS0>(acr, aci, Vt, (int)ldv, RPW * w, (const double*)Np, l);
+        }
         constexpr int SC = 4;
 #pragma unroll 2
-        for (int s0 = 0; s0 < KS0; s0 += SC) {
+        for (int s0 = 0; s0 < (fullv ? 0 : KS0); s0 += SC) {
             double vr[RB][SC], vi[RB][SC], br[SC][CT], bi[SC][CT];
 #pragma unroll
             for (int rb = 0; rb < RB; rb++) {
