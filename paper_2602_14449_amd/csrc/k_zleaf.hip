@@ -820,7 +820,8 @@ __global__ __launch_bounds__(256) void k_zkchain(ZLevel L, dcplx* Cfin) {
                     sr += a.re * b.re - a.im * b.im;
                     si += a.re * b.im + a.im * b.re;
                 }
-            Tt[((i % KS) * CT + j / 16) * 64 + 16 * (i / KS) + (j % 16)] = dcplx{-sr, -si};
+            // row i of K is K-step i / 4 of lane group i % 4 (the split of zprod_full)
+            Tt[((i >> 2) * CT + j / 16) * 64 + 16 * (i & 3) + (j % 16)] = dcplx{-sr, -si};
             if (!plain) Cs[i * LD + j] = dcplx{Cs[i * LD + j].re - sr, Cs[i * LD + j].im - si};
         }
     }
@@ -872,7 +873,10 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zrows(ZLevel L, const dcplx* Cf
                     }
                 }
     }
-    // - Y_t K_t (the stored -K_t), all KS K-steps' loads issued together
+    // - Y_t K_t (the stored -K_t, K split 4 s + lane / 16)
+    const bool fullk = trows == TB && k == KP;
+    if (fullk) zprod_full<RB, CT, KS>(acr, aci, Yt, ldy, RPW * w, Kg, l);
+    else
 #pragma unroll
     for (int rb = 0; rb < RB; rb++) {
         const int yr = RPW * w + 16 * rb + cl;
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(ZNW * 64, 2) void k_zrows(ZLevel L, const dcplx* Cf
 #pragma unroll
         for (int s = 0; s < KS; s++) {
             double2 z = make_double2(0.0, 0.0);
-            if (yr < trows && g * KS + s < k) z = ld2(Yt + 2 * (yr * ldy + g * KS + s));
+            if (yr < trows && 4 * s + g < k) z = ld2(Yt + 2 * (yr * ldy + 4 * s + g));
             ar[s] = z.x;
             ai[s] = z.y;
         }
