@@ -201,7 +201,7 @@ __global__ void k_zero_ints(int* p, int n) {
 template <int KP, int RBO>
 constexpr size_t batched_lds() {
     constexpr size_t pre = (size_t)2 * 64 * (KP + 1);
-    constexpr size_t qr = (size_t)64 * 65 + 19 * 64 + 16;
+    constexpr size_t qr = (size_t)qr_top_lds(64);
     constexpr size_t leaf = LeafLds<KP, RBO>::total;
     constexpr size_t form = FormLds<KP>::total;
     return (pre > qr ? (pre > leaf ? (pre > form ? pre : form) : (leaf > form ? leaf : form))

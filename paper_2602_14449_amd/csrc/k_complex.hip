@@ -301,7 +301,8 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
     cplx* taus = M + n * ld;     // n
     cplx* wv = taus + n;         // n
     cplx* sc = wv + n;           // 2
-    double* red = (double*)(sc + 2);  // 8
+    cplx* ub = sc + 2;           // n: the reflector being applied in the formation
+    double* red = (double*)(ub + n);  // 8
     double* sgn = red + 8;       // n
     const int tid = threadIdx.x;
     for (int e = tid; e < n * n; e += CW) M[(e / n) * ld + e % n] = Vt[(int64_t)(e / n) * ldv + e % n];
@@ -362,12 +363,15 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
     }
     for (int i = tid; i < n; i += CW) sgn[i] = (M[i * ld + i].re < 0.0) ? -1.0 : 1.0;
     __syncthreads();
-    // Q in place (backward accumulation): column block of H_j applied to e-columns
+    // Q in place (backward accumulation): H_j applied to the formed columns
+    // c > j, two barriers per column.  The dots copy u_j into ub, so that the
+    // update reads it there while column j is overwritten by H_j e_j in the
+    // same phase (row j of a formed column c > j is zero).
     for (int j = n - 1; j >= 0; j--) {
         const cplx tau = taus[j];
         if (j < n - 1) {
             {
-                // row j of a formed column c > j is zero; a quad per column
+                // a quad per column
                 const int cc = j + 1 + (tid >> 2), q = tid & 3;
                 double sr = 0.0, si = 0.0;
                 if (cc < n)
@@ -380,16 +384,16 @@ __global__ __launch_bounds__(CW) void k_zqr_top(int n, const cplx* __restrict__ 
                 si = sum_quad(si);
                 if (cc < n && q == 0) wv[cc] = cmk(sr, si);
             }
+            for (int i = j + 1 + tid; i < n; i += CW) ub[i] = M[i * ld + j];
             __syncthreads();
             for (int e = tid; e < (n - j) * (n - j - 1); e += CW) {
                 const int i = j + e / (n - j - 1), cc = j + 1 + e % (n - j - 1);
-                const cplx u = (i == j) ? cmk(1.0, 0.0) : M[i * ld + j];
+                const cplx u = (i == j) ? cmk(1.0, 0.0) : ub[i];
                 M[i * ld + cc] = csub(M[i * ld + cc], cmul(u, cmul(tau, wv[cc])));
             }
-            __syncthreads();
         }
         for (int i = tid; i < n; i += CW) {
-            if (i > j) M[i * ld + j] = cmul(cmk(-tau.re, -tau.im), M[i * ld + j]);
+            if (i > j) M[i * ld + j] = cmul(cmk(-tau.re, -tau.im), ub[i]);
             else if (i == j) M[j * ld + j] = cmk(1.0 - tau.re, -tau.im);
             else M[i * ld + j] = cmk(0.0, 0.0);
         }
@@ -584,7 +588,7 @@ hipError_t launch_zform(int kp, const ZLevel& L, hipStream_t st) {
 hipError_t launch_zqr_top(int n, const void* Vt, int64_t ldv, void* P, void* T, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (n > 64) return hipErrorInvalidValue;
-    const size_t shm = ((size_t)n * (n + 1) + 2 * n + 2) * sizeof(cplx) + (8 + n) * sizeof(double);
+    const size_t shm = ((size_t)n * (n + 1) + 3 * n + 2) * sizeof(cplx) + (8 + n) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_zqr_top, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -16,7 +16,7 @@ namespace tho {
 // Any block size that is a multiple of 128 (n > 64) or 64 (n <= 64) works;
 // the columns are spread over CW lanes and the rows over blockDim / CW
 // groups.  LDS: qr_top_lds(n) doubles at sm.
-__host__ __device__ inline int qr_top_lds(int n) { return n * (n + 1) + 16 * n + 3 * n + 16; }
+__host__ __device__ constexpr int qr_top_lds(int n) { return n * (n + 1) + 16 * n + 4 * n + 16; }
 
 __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t ldv, double* __restrict__ P,
                                    double* __restrict__ T, double* sm) {
@@ -28,7 +28,8 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
     double* wv = part + 16 * n;     // n: w_c of the current reflector
     double* taus = wv + n;          // n
     double* sgn = taus + n;         // n: sign of R_jj
-    double* red = sgn + n;          // 16 scalars
+    double* ub = sgn + n;           // n: the reflector being applied in the formation
+    double* red = ub + n;           // 16 scalars
     const int tid = threadIdx.x;
     const int c = tid % CW, rg = tid / CW;  // column, row group
     for (int e = tid; e < n * n; e += blockDim.x) M[(e / n) * ld + (e % n)] = Vt[(int64_t)(e / n) * ldv + (e % n)];
@@ -91,7 +92,11 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
     // keep the diagonal signs before Q overwrites M
     if (tid < n) sgn[tid] = (M[tid * ld + tid] < 0.0) ? -1.0 : 1.0;
     __syncthreads();
-    // form Q in place (backward accumulation of the reflectors)
+    // form Q in place (backward accumulation of the reflectors), two
+    // barriers per column: the dots copy the reflector u_j into ub, so that
+    // the update reads it there while column j is overwritten by its formed
+    // value H_j e_j in the same phase.  Row j of an already formed column
+    // c > j is zero, so its update is -tau w_c and needs no read.
     for (int j = n - 1; j >= 0; j--) {
         const double tau = taus[j];
         if (j < n - 1) {
@@ -100,24 +105,18 @@ __device__ inline void qr_top_body(int n, const double* __restrict__ Vt, int64_t
                 for (int i = j + 1 + rg; i < n; i += RG) s += M[i * ld + j] * M[i * ld + c];
                 part[rg * n + c] = s;
             }
+            for (int i = j + 1 + tid; i < n; i += blockDim.x) ub[i] = M[i * ld + j];
             __syncthreads();
-            double rowj = 0.0;
             if (c < n && c > j) {
-                // row j of an already formed column c > j is zero; its
-                // update is stored after the barrier (every thread of the
-                // column reads it first)
-                rowj = M[j * ld + c];
-                double wc = rowj;
+                double wc = 0.0;
                 for (int r = 0; r < RG; r++) wc += part[r * n + c];
                 const double tw = tau * wc;
-                rowj -= tw;
-                for (int i = j + 1 + rg; i < n; i += RG) M[i * ld + c] -= tw * M[i * ld + j];
+                for (int i = j + 1 + rg; i < n; i += RG) M[i * ld + c] -= tw * ub[i];
+                if (rg == 0) M[j * ld + c] = -tw;
             }
-            __syncthreads();
-            if (c < n && c > j && rg == 0) M[j * ld + c] = rowj;
         }
         if (tid < n) {
-            if (tid > j) M[tid * ld + j] = -tau * M[tid * ld + j];
+            if (tid > j) M[tid * ld + j] = -tau * ub[tid];
             else if (tid == j) M[j * ld + j] = 1.0 - tau;
             else M[tid * ld + j] = 0.0;
         }
