@@ -19,7 +19,7 @@ Definitions followed
     T = I + R1^* is the form analysed in Appendix B.2; it equals
     I - V_top^* P whenever Q1 is unitary (tested).
 
-Readings taken where the paper is silent (listed in the design doc as well)
+Readings taken where the paper is silent
   * Intra-block QR: column Householder with the nonnegative-diagonal phase
     convention (``householder.qr_pos``).
   * S is computed as P^* times the top block of H^* A (as in the method's
